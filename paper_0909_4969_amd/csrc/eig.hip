@@ -1,0 +1,828 @@
+// Float64 top-R eigensolve of a Gram matrix and the factor update it
+// feeds (Alg. 1 HOSVD loop and Alg. 2 inner loop: "A <- r leading left
+// singular vectors"; Section 2.2 on the SVD), plus the fit and the core
+// (eq. eqcore, the last line of Alg. 1/2) with its norm (eq. norm).
+//
+// Sides up to 64: one workgroup runs cyclic two-sided Jacobi (Golub & Van
+// Loan, "Matrix Computations", Sec. 8.5) on the whole matrix in LDS with
+// the round-robin parallel ordering, optionally warm-started from the
+// previous eigenvector matrix of the same mode (W = V^T G V is close to
+// diagonal once HOOI settles, and Jacobi converges quadratically).
+// Larger sides: block subspace iteration with float64 CholeskyQR2
+// orthonormalisation and Rayleigh-Ritz on a 64-column block (the projected
+// 64 x 64 problem goes to the Jacobi kernel), until the residuals of the
+// top R Ritz pairs fall below 1e-12 of the largest.
+//
+// The factor of a row-side Gram is its top-R eigenvectors.  For a
+// column-side Gram of M (rows i, columns j) it is M v / sqrt(lambda),
+// orthonormalised again by CholeskyQR2 in float64.  Every factor then gets
+// the sign rule: in each column the entry of largest magnitude is positive
+// (lowest row on ties).
+#include <cmath>
+
+#include "solver.h"
+
+namespace mach {
+
+hipError_t launch_gram_y(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
+                         hipStream_t st);
+hipError_t launch_gram_xhat(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
+                            char* ws, int n, hipStream_t st);
+
+namespace {
+
+constexpr int kMaxSweeps = 40;
+
+__device__ __forceinline__ void jpair(int r, int k, int np, int* p, int* q) {
+  int m = np - 1, a, b;
+  if (k == 0) {
+    a = r;
+    b = m;
+  } else {
+    a = (r + k) % m;
+    b = (r - k + m) % m;
+  }
+  *p = a < b ? a : b;
+  *q = a < b ? b : a;
+}
+
+struct Status {
+  const SampleHdr* hdr;
+  int32_t* st;        // solver status word
+  const int32_t* done;  // optional early-exit flag (converged); may be null
+  __device__ __forceinline__ bool skip() const {
+    return hdr->status != 0 || *st != 0 || (done && *done);
+  }
+};
+
+__device__ void block_sum2(double& a, double& b, double (*red)[4]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+  }
+  __syncthreads();
+  a = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+  b = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  __syncthreads();
+}
+
+struct JacArgs {
+  const double* G;     // n x n symmetric
+  uint32_t n;
+  double* V;           // in: warm start if *tag == tagval; out: eigenvectors (columns, sorted)
+  double* lam;         // out: eigenvalues, descending
+  int32_t* tag;
+  int32_t tagval;
+  Status s;
+};
+
+__global__ __launch_bounds__(256) void k_jacobi_small(JacArgs a) {
+  if (a.s.skip()) return;
+  __shared__ double A[64][65];
+  __shared__ double B[64][65];
+  __shared__ double C[64][65];
+  __shared__ double rc[32], rs[32], rt[32];
+  __shared__ int rp[32], rq[32], rk[64];
+  __shared__ double red[2][4];
+  const int n = (int)a.n, np = (n + 1) & ~1, tid = threadIdx.x;
+  const bool warm = (*a.tag == a.tagval);
+  for (int e = tid; e < np * np; e += 256) {
+    int x = e / np, y = e % np;
+    A[x][y] = (x < n && y < n) ? a.G[x * n + y] : 0.0;
+    B[x][y] = (warm && x < n && y < n) ? a.V[x * n + y] : (x == y ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (warm) {
+    for (int e = tid; e < np * np; e += 256) {
+      int x = e / np, y = e % np;
+      double s = 0.0;
+      for (int z = 0; z < np; ++z) s = fma(A[x][z], B[z][y], s);
+      C[x][y] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < np * np; e += 256) {
+      int x = e / np, y = e % np;
+      double s = 0.0;
+      for (int z = 0; z < np; ++z) s = fma(B[z][x], C[z][y], s);
+      A[x][y] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < np * np; e += 256) {
+      int x = e / np, y = e % np;
+      if (x < y) {
+        double m = 0.5 * (A[x][y] + A[y][x]);
+        A[x][y] = m;
+        A[y][x] = m;
+      }
+    }
+    __syncthreads();
+  }
+  const int npairs = np / 2;
+  bool conv = false;
+  for (int sweep = 0; sweep <= kMaxSweeps; ++sweep) {
+    double off = 0.0, dg = 0.0;
+    for (int e = tid; e < np * np; e += 256) {
+      int x = e / np, y = e % np;
+      double v = A[x][y];
+      if (x == y) dg += v * v;
+      else off += v * v;
+    }
+    block_sum2(off, dg, red);
+    conv = (off <= 1e-26 * dg) || dg == 0.0;
+    if (conv || sweep == kMaxSweeps) break;
+    for (int r = 0; r < np - 1; ++r) {
+      if (tid < npairs) {
+        int p, q;
+        jpair(r, tid, np, &p, &q);
+        double apq = A[p][q], app = A[p][p], aqq = A[q][q];
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (fabs(apq) > 1e-300) {
+          double th = (aqq - app) / (2.0 * apq);
+          t = fabs(th) > 1e150 ? 0.5 / th : copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+        }
+        rc[tid] = c;
+        rs[tid] = s;
+        rt[tid] = t;
+        rp[tid] = p;
+        rq[tid] = q;
+      }
+      __syncthreads();
+      for (int blk = tid; blk < npairs * npairs; blk += 256) {
+        int ia = blk / npairs, ib = blk % npairs;
+        int pa = rp[ia], qa = rq[ia], pb = rp[ib], qb = rq[ib];
+        if (ia == ib) {
+          double t = rt[ia], apq = A[pa][qa];
+          A[pa][pa] -= t * apq;
+          A[qa][qa] += t * apq;
+          A[pa][qa] = 0.0;
+          A[qa][pa] = 0.0;
+        } else {
+          double ca = rc[ia], sa = rs[ia], cb = rc[ib], sb = rs[ib];
+          double w11 = A[pa][pb], w12 = A[pa][qb], w21 = A[qa][pb], w22 = A[qa][qb];
+          double r11 = ca * w11 - sa * w21, r12 = ca * w12 - sa * w22;
+          double r21 = sa * w11 + ca * w21, r22 = sa * w12 + ca * w22;
+          A[pa][pb] = cb * r11 - sb * r12;
+          A[pa][qb] = sb * r11 + cb * r12;
+          A[qa][pb] = cb * r21 - sb * r22;
+          A[qa][qb] = sb * r21 + cb * r22;
+        }
+      }
+      for (int it = tid; it < np * npairs; it += 256) {
+        int x = it / npairs, ib = it % npairs;
+        int pb = rp[ib], qb = rq[ib];
+        double cb = rc[ib], sb = rs[ib];
+        double v1 = B[x][pb], v2 = B[x][qb];
+        B[x][pb] = cb * v1 - sb * v2;
+        B[x][qb] = sb * v1 + cb * v2;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid < n) {
+    double lx = A[tid][tid];
+    int rank = 0;
+    for (int y = 0; y < n; ++y) {
+      double ly = A[y][y];
+      rank += (ly > lx) || (ly == lx && y < tid);
+    }
+    rk[tid] = rank;
+    a.lam[rank] = lx;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += 256) {
+    int row = e / n, x = e % n;
+    a.V[row * n + rk[x]] = B[row][x];
+  }
+  if (tid == 0) {
+    *a.tag = a.tagval;
+    if (!conv) atomicCAS(a.s.st, 0, MACH_ENOCONV);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense float64 helpers for the subspace solver and CholeskyQR2
+// ---------------------------------------------------------------------------
+
+// C[M x N] = A[M x K] * B[K x N] (row-major, leading dims), N <= 64.
+__global__ __launch_bounds__(256) void k_gemm64(const double* __restrict__ A, uint32_t lda,
+                                                const double* __restrict__ B, uint32_t ldb,
+                                                double* __restrict__ C, uint32_t ldc, uint32_t M,
+                                                uint32_t K, uint32_t N, Status s) {
+  if (s.skip()) return;
+  __shared__ double As[64][33];
+  __shared__ double Bs[32][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const uint32_t m0 = blockIdx.x * 64;
+  double acc[4][4] = {};
+  for (uint32_t k0 = 0; k0 < K; k0 += 32) {
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      int r = e >> 5, c = e & 31;
+      uint32_t m = m0 + r, k = k0 + c;
+      As[r][c] = (m < M && k < K) ? A[(size_t)m * lda + k] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+      int r = e >> 6, c = e & 63;
+      uint32_t k = k0 + r;
+      Bs[r][c] = (k < K && (uint32_t)c < N) ? B[(size_t)k * ldb + c] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 32; ++kk) {
+      double u[4], w[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        u[i] = As[ty * 4 + i][kk];
+        w[i] = Bs[kk][tx * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t m = m0 + ty * 4 + i, n = tx * 4 + j;
+      if (m < M && n < N) C[(size_t)m * ldc + n] = acc[i][j];
+    }
+}
+
+// part[chunk][x][y] = sum over the chunk's rows m of A[m][x] * B[m][y]  (x, y < n <= 64)
+__global__ __launch_bounds__(256) void k_atb_partial(const double* __restrict__ A, uint32_t lda,
+                                                     const double* __restrict__ B, uint32_t ldb,
+                                                     uint32_t M, uint32_t n, uint32_t rows,
+                                                     double* __restrict__ part, Status s) {
+  if (s.skip()) return;
+  __shared__ double As[32][65];
+  __shared__ double Bs[32][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const uint32_t r0 = blockIdx.x * rows, r1 = min(M, r0 + rows);
+  double acc[4][4] = {};
+  for (uint32_t m0 = r0; m0 < r1; m0 += 32) {
+    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+      int r = e >> 6, c = e & 63;
+      uint32_t m = m0 + r;
+      bool ok = m < r1 && (uint32_t)c < n;
+      As[r][c] = ok ? A[(size_t)m * lda + c] : 0.0;
+      Bs[r][c] = ok ? B[(size_t)m * ldb + c] : 0.0;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < 32; ++rr) {
+      double u[4], w[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        u[i] = As[rr][tx * 4 + i];
+        w[i] = Bs[rr][ty * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  double* o = part + (size_t)blockIdx.x * n * n;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t x = tx * 4 + i, y = ty * 4 + j;
+      if (x < n && y < n) o[x * n + y] = acc[i][j];
+    }
+}
+
+__global__ void k_small_reduce(const double* __restrict__ part, uint32_t nchunk, uint32_t n2,
+                               double* __restrict__ out, Status s) {
+  if (s.skip()) return;
+  uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n2) return;
+  double acc = 0.0;
+  for (uint32_t c = 0; c < nchunk; ++c) acc += part[(size_t)c * n2 + e];
+  out[e] = acc;
+}
+
+// X[M x n] <- X L^{-T} where L L^T = S + shift*tr(S)/n I (S: n x n Gram of X).
+// Every workgroup factors S itself; one wave per row solves the triangle.
+__global__ __launch_bounds__(256) void k_cholqr_apply(double* __restrict__ X, uint32_t ldx, uint32_t M,
+                                                      uint32_t n, const double* __restrict__ S,
+                                                      double shift, Status s) {
+  if (s.skip()) return;
+  __shared__ double L[64][65];
+  __shared__ double trs;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    int x = e >> 6, y = e & 63;
+    L[x][y] = (x < (int)n && y < (int)n) ? S[x * n + y] : (x == y ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (uint32_t i = 0; i < n; ++i) t += L[i][i];
+    trs = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < n) L[threadIdx.x][threadIdx.x] += shift * trs / n;
+  __syncthreads();
+  for (uint32_t j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double d = L[j][j];
+      L[j][j] = d > 1e-300 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    for (uint32_t i = j + 1 + threadIdx.x; i < n; i += 256) L[i][j] /= L[j][j];
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < n * n; e += 256) {
+      uint32_t i = e / n, k = e % n;
+      if (i > j && k > j && k <= i) L[i][k] -= L[i][j] * L[k][j];
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (uint32_t m = blockIdx.x * 4 + wv; m < M; m += gridDim.x * 4) {
+    double z = lane < (int)n ? X[(size_t)m * ldx + lane] : 0.0;
+    double x = 0.0;
+    for (uint32_t j = 0; j < n; ++j) {
+      double xj = __shfl(z, j, 64) / L[j][j];
+      if (lane == (int)j) x = xj;
+      if (lane > (int)j && lane < (int)n) z -= xj * L[lane][j];
+    }
+    if (lane < (int)n) X[(size_t)m * ldx + lane] = x;
+  }
+}
+
+// Deterministic start block for the subspace iteration (hash of position).
+__global__ void k_ss_init(double* __restrict__ Q, uint32_t ldq, uint32_t M, uint32_t n,
+                          const int32_t* tag, int32_t tagval, Status s) {
+  if (s.skip() || *tag == tagval) return;
+  uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * n) return;
+  uint32_t i = e / n, j = e % n;
+  uint32_t h = i * 0x9E3779B1u ^ (j + 1) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  Q[(size_t)i * ldq + j] = (double)(h >> 8) * (1.0 / 16777216.0) - 0.5;
+}
+
+__global__ void k_copy64(const double* __restrict__ src, double* __restrict__ dst, uint32_t n,
+                         Status s) {
+  if (s.skip()) return;
+  uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e < n) dst[e] = src[e];
+}
+
+// Residuals of the top R Ritz pairs: converged if all
+// ||Z2[:,r] - theta_r Qr[:,r]|| <= tol * theta_0; single workgroup.
+__global__ __launch_bounds__(256) void k_ss_check(const double* __restrict__ Z2, const double* __restrict__ Qr,
+                                                  uint32_t ld, uint32_t M, const double* __restrict__ theta,
+                                                  uint32_t R, double tol, int32_t* done, int last,
+                                                  Status s) {
+  if (s.skip()) return;
+  __shared__ double res[16][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc[16];
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (uint32_t m = threadIdx.x; m < M; m += 256)
+    for (uint32_t r = 0; r < R; ++r) {
+      double d = Z2[(size_t)m * ld + r] - theta[r] * Qr[(size_t)m * ld + r];
+      acc[r] += d * d;
+    }
+  for (int r = 0; r < 16; ++r) {
+    double v = acc[r];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) res[r][w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double worst = 0.0;
+    for (uint32_t r = 0; r < R; ++r) {
+      double v = sqrt((res[r][0] + res[r][1]) + (res[r][2] + res[r][3]));
+      worst = v > worst ? v : worst;
+    }
+    double ref = fabs(theta[0]);
+    if (worst <= tol * ref) *done = 1;
+    else if (last && worst > 1e-8 * ref) atomicCAS(s.st, 0, MACH_ENOCONV);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Factor update
+// ---------------------------------------------------------------------------
+
+// Aw[i][r] = V[i][r] (row-side Gram: the eigenvectors are the factor).
+__global__ void k_take_cols(const double* __restrict__ V, uint32_t ldv, uint32_t I, uint32_t R,
+                            double* __restrict__ Aw, Status s) {
+  if (s.skip()) return;
+  uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= I * 16) return;
+  uint32_t i = e >> 4, r = e & 15;
+  Aw[e] = r < R ? V[(size_t)i * ldv + r] : 0.0;
+}
+
+// Column-side Gram of M = Y_(k) (dense float32): Aw[i][r] = sum_j M[i, j] V[j][r] / sqrt(lam_r).
+__global__ __launch_bounds__(256) void k_backproject_dense(const float* __restrict__ Y, uint32_t I,
+                                                           uint32_t Q, uint32_t J, FastDiv fQ,
+                                                           const double* __restrict__ V, uint32_t ldv,
+                                                           const double* __restrict__ lam, uint32_t R,
+                                                           double* __restrict__ Aw, Status s) {
+  if (s.skip()) return;
+  uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!(lam[R - 1] > 1e-13 * lam[0])) atomicCAS(s.st, 0, MACH_EDEGENERATE);
+  }
+  if (i >= I) return;
+  double acc[16];
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (uint32_t j = 0; j < J; ++j) {
+    uint32_t q = fQ.div(j);
+    double y = (double)Y[(size_t)q * I * Q + (size_t)i * Q + (j - q * Q)];
+    const double* v = V + (size_t)j * ldv;
+    for (uint32_t r = 0; r < R; ++r) acc[r] = fma(y, v[r], acc[r]);
+  }
+  for (uint32_t r = 0; r < 16; ++r)
+    Aw[(size_t)i * 16 + r] = r < R ? acc[r] / sqrt(fmax(lam[r], 1e-300)) : 0.0;
+}
+
+// Same for the sampled unfolding Xhat_(n): element (i, j) at off(j) + i * Q.
+__global__ __launch_bounds__(256) void k_backproject_xhat(const uint64_t* __restrict__ bitmap,
+                                                          const uint32_t* __restrict__ wrank,
+                                                          const Entry* __restrict__ coo, uint32_t I,
+                                                          uint32_t Q, uint32_t J, FastDiv fQ,
+                                                          const double* __restrict__ V, uint32_t ldv,
+                                                          const double* __restrict__ lam, uint32_t R,
+                                                          double* __restrict__ Aw, Status s) {
+  if (s.skip()) return;
+  uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!(lam[R - 1] > 1e-13 * lam[0])) atomicCAS(s.st, 0, MACH_EDEGENERATE);
+  }
+  if (i >= I) return;
+  double acc[16];
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (uint32_t j = 0; j < J; ++j) {
+    uint32_t q = fQ.div(j);
+    uint32_t l = q * I * Q + i * Q + (j - q * Q);
+    uint64_t word = bitmap[l >> 6];
+    uint32_t b = l & 63;
+    if (!((word >> b) & 1ull)) continue;
+    uint64_t below = b ? (word & ((~0ull) >> (64 - b))) : 0ull;
+    double x = (double)coo[wrank[l >> 6] + (uint32_t)__popcll(below)].v;
+    const double* v = V + (size_t)j * ldv;
+    for (uint32_t r = 0; r < R; ++r) acc[r] = fma(x, v[r], acc[r]);
+  }
+  for (uint32_t r = 0; r < 16; ++r)
+    Aw[(size_t)i * 16 + r] = r < R ? acc[r] / sqrt(fmax(lam[r], 1e-300)) : 0.0;
+}
+
+// Per-chunk column maxima of |Aw| (value, then lowest row).
+__global__ __launch_bounds__(256) void k_colmax_partial(const double* __restrict__ Aw, uint32_t I,
+                                                        uint32_t R, uint32_t rows,
+                                                        double* __restrict__ pv, uint32_t* __restrict__ pi,
+                                                        Status s) {
+  if (s.skip()) return;
+  __shared__ double bv[256];
+  __shared__ uint32_t bi[256];
+  uint32_t r = threadIdx.x & 15, g = threadIdx.x >> 4;
+  uint32_t i0 = blockIdx.x * rows, i1 = min(I, i0 + rows);
+  double best = -1.0;
+  uint32_t bidx = 0xffffffffu;
+  for (uint32_t i = i0 + g; i < i1; i += 16) {
+    double v = fabs(Aw[(size_t)i * 16 + r]);
+    if (v > best) {
+      best = v;
+      bidx = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    double b = -1.0;
+    uint32_t bx = 0xffffffffu;
+    for (int gg = 0; gg < 16; ++gg) {
+      double v = bv[gg * 16 + threadIdx.x];
+      uint32_t ix = bi[gg * 16 + threadIdx.x];
+      if (v > b || (v == b && ix < bx)) {
+        b = v;
+        bx = ix;
+      }
+    }
+    pv[blockIdx.x * 16 + threadIdx.x] = b;
+    pi[blockIdx.x * 16 + threadIdx.x] = bx;
+  }
+}
+
+// Applies the sign rule, writes the float64 factor (I x R) and the float32
+// working copy (I x 16, zero padded).
+__global__ __launch_bounds__(256) void k_sign_store(const double* __restrict__ Aw, uint32_t I, uint32_t R,
+                                                    const double* __restrict__ pv,
+                                                    const uint32_t* __restrict__ pi, uint32_t nchunk,
+                                                    double* __restrict__ Aout, float* __restrict__ af,
+                                                    Status s) {
+  if (s.skip()) return;
+  __shared__ double sg[16];
+  if (threadIdx.x < 16) {
+    double b = -1.0;
+    uint32_t bx = 0xffffffffu;
+    for (uint32_t c = 0; c < nchunk; ++c) {
+      double v = pv[c * 16 + threadIdx.x];
+      uint32_t ix = pi[c * 16 + threadIdx.x];
+      if (v > b || (v == b && ix < bx)) {
+        b = v;
+        bx = ix;
+      }
+    }
+    double sgn = 1.0;
+    if (threadIdx.x < R && bx < I && Aw[(size_t)bx * 16 + threadIdx.x] < 0.0) sgn = -1.0;
+    sg[threadIdx.x] = sgn;
+  }
+  __syncthreads();
+  uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= I * 16) return;
+  uint32_t i = e >> 4, r = e & 15;
+  double v = r < R ? sg[r] * Aw[e] : 0.0;
+  if (r < R) Aout[(size_t)i * R + r] = v;
+  af[e] = (float)v;
+}
+
+// fit = 1 - sqrt(max(0, ||Xhat||^2 - ||G||^2)) / ||Xhat||, with
+// ||G||^2 = sum of the top R eigenvalues of the last mode's Gram / p^2.
+__global__ void k_fit(const double* __restrict__ lam, uint32_t R, const SampleHdr* hdr,
+                      const int32_t* st, double* fit, double* core2_out) {
+  if (hdr->status != 0 || *st != 0) return;
+  double p2 = hdr->p * hdr->p;
+  double g2 = 0.0;
+  for (uint32_t r = 0; r < R; ++r) g2 += lam[r];
+  g2 /= p2;
+  double x2 = hdr->sumsq / p2;
+  if (fit) *fit = 1.0 - sqrt(fmax(0.0, x2 - g2)) / sqrt(x2);
+  if (core2_out) *core2_out = g2;
+}
+
+// G[(q*O + o)*R + r] = (1/p) sum_i A[i][r] Y[(o*I + i)*Q + q]
+__global__ void k_core(const float* __restrict__ Y, uint32_t O, uint32_t I, uint32_t Q,
+                       const double* __restrict__ A, uint32_t R, double* __restrict__ G,
+                       const SampleHdr* hdr, const int32_t* st) {
+  if (hdr->status != 0 || *st != 0) return;
+  uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= O * Q * R) return;
+  uint32_t r = e % R, t = e / R;
+  uint32_t o = t % O, q = t / O;
+  double acc = 0.0;
+  for (uint32_t i = 0; i < I; ++i)
+    acc = fma(A[(size_t)i * R + r], (double)Y[((size_t)o * I + i) * Q + q], acc);
+  G[e] = acc / hdr->p;
+}
+
+__global__ __launch_bounds__(256) void k_norm2(const double* __restrict__ G, uint32_t n, double* out,
+                                               const SampleHdr* hdr, const int32_t* st) {
+  if (hdr->status != 0 || *st != 0) return;
+  __shared__ double red[2][4];
+  double a = 0.0, b = 0.0;
+  for (uint32_t e = threadIdx.x; e < n; e += 256) a += G[e] * G[e];
+  block_sum2(a, b, red);
+  if (threadIdx.x == 0) *out = a;
+}
+
+__global__ void k_solver_init(int32_t* st, int32_t* tags, int ntags) {
+  int t = threadIdx.x;
+  if (t == 0) *st = 0;
+  if (t < ntags) tags[t] = 0;
+}
+
+}  // namespace
+}  // namespace mach
+
+namespace mach {
+namespace {
+
+struct Ctx {
+  const SolverLayout* SL;
+  char* ws;
+  const SampleHdr* hdr;
+  hipStream_t st;
+  int32_t* status() const { return (int32_t*)(ws + SL->status); }
+  int32_t* tags() const { return (int32_t*)(ws + SL->status + 16); }
+  Status stat(bool with_done = false) const {
+    Status s;
+    s.hdr = hdr;
+    s.st = status();
+    s.done = with_done ? tags() + kTagDone : nullptr;
+    return s;
+  }
+  double* d(size_t off) const { return (double*)(ws + off); }
+};
+
+inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+__global__ void k_set_int(int32_t* p, int32_t v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+void cholqr2(const Ctx& c, double* X, uint32_t ldx, uint32_t M, uint32_t n, bool with_done) {
+  Status s = c.stat(with_done);
+  uint32_t nchunk = cdiv(M, 256);
+  if (nchunk > 64) nchunk = 64;
+  if (nchunk < 1) nchunk = 1;
+  uint32_t rows = cdiv(M, nchunk);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, X, ldx, X, ldx, M, n, rows,
+                       c.d(c.SL->part), s);
+    hipLaunchKernelGGL(k_small_reduce, dim3(cdiv(n * n, 256)), dim3(256), 0, c.st, c.d(c.SL->part),
+                       nchunk, n * n, c.d(c.SL->small), s);
+    uint32_t g = cdiv(M, 4);
+    if (g > 128) g = 128;
+    hipLaunchKernelGGL(k_cholqr_apply, dim3(g), dim3(256), 0, c.st, X, ldx, M, n, c.d(c.SL->small),
+                       pass == 0 ? 1e-15 : 0.0, s);
+  }
+}
+
+void gemm(const Ctx& c, const double* A, uint32_t lda, const double* B, uint32_t ldb, double* C,
+          uint32_t ldc, uint32_t M, uint32_t K, uint32_t N, bool with_done) {
+  hipLaunchKernelGGL(k_gemm64, dim3(cdiv(M, 64)), dim3(256), 0, c.st, A, lda, B, ldb, C, ldc, M, K,
+                     N, c.stat(with_done));
+}
+
+void jacobi(const Ctx& c, const double* G, uint32_t n, double* V, double* lam, int32_t* tag,
+            int32_t tagval, bool with_done) {
+  JacArgs a;
+  a.G = G;
+  a.n = n;
+  a.V = V;
+  a.lam = lam;
+  a.tag = tag;
+  a.tagval = tagval;
+  a.s = c.stat(with_done);
+  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(256), 0, c.st, a);
+}
+
+// Top eigenpairs of the s x s matrix G (s > 64) by block subspace iteration
+// with Rayleigh-Ritz every 4 steps.  Q (s x 64, ld 64) holds the block (warm
+// start if *tag == tagval); on return its first columns are the Ritz
+// vectors, lam (64) the Ritz values, descending.
+void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double* Q, double* lam,
+                   int32_t* tag, int32_t tagval, int maxit) {
+  const uint32_t b = s < kBlock ? s : kBlock;
+  int32_t* tags = c.tags();
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagDone, 0);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagRR, 0);
+  hipLaunchKernelGGL(k_ss_init, dim3(cdiv((uint64_t)s * b, 256)), dim3(256), 0, c.st, Q, kBlock, s,
+                     b, tag, tagval, c.stat());
+  cholqr2(c, Q, kBlock, s, b, false);
+  double* Z = c.d(c.SL->Zs);
+  double* Z2 = c.d(c.SL->Z2s);
+  double* Qr = c.d(c.SL->Qrs);
+  double* H = c.d(c.SL->H);
+  double* VH = c.d(c.SL->VH);
+  double* lamH = c.d(c.SL->lamH);
+  Status sd = c.stat(true);
+  for (int it = 0; it < maxit; ++it) {
+    gemm(c, G, s, Q, kBlock, Z, kBlock, s, s, b, true);
+    cholqr2(c, Z, kBlock, s, b, true);
+    hipLaunchKernelGGL(k_copy64, dim3(cdiv((uint64_t)s * kBlock, 256)), dim3(256), 0, c.st, Z, Q,
+                       s * kBlock, sd);
+    bool last = it == maxit - 1;
+    if (it % 4 == 3 || last) {
+      gemm(c, G, s, Q, kBlock, Z, kBlock, s, s, b, true);
+      uint32_t nchunk = cdiv(s, 256);
+      if (nchunk > 64) nchunk = 64;
+      uint32_t rows = cdiv(s, nchunk);
+      hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, Q, kBlock, Z, kBlock, s, b,
+                         rows, c.d(c.SL->part), sd);
+      hipLaunchKernelGGL(k_small_reduce, dim3(cdiv(b * b, 256)), dim3(256), 0, c.st, c.d(c.SL->part),
+                         nchunk, b * b, H, sd);
+      jacobi(c, H, b, VH, lamH, tags + kTagRR, 0x52520000 | (int32_t)b, true);
+      gemm(c, Q, kBlock, VH, b, Qr, kBlock, s, b, b, true);
+      gemm(c, Z, kBlock, VH, b, Z2, kBlock, s, b, b, true);
+      hipLaunchKernelGGL(k_copy64, dim3(cdiv((uint64_t)s * kBlock, 256)), dim3(256), 0, c.st, Qr, Q,
+                         s * kBlock, sd);
+      hipLaunchKernelGGL(k_copy64, dim3(1), dim3(256), 0, c.st, lamH, lam, b, sd);
+      hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, Z2, Qr, kBlock, s, lamH, R, 1e-12,
+                         tags + kTagDone, last ? 1 : 0, c.stat(true));
+    }
+  }
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tag, tagval);
+}
+
+// Sign rule and stores from Aw (I x 16 float64).
+void sign_store(const Ctx& c, uint32_t I, uint32_t R, double* Aout, float* af) {
+  uint32_t nchunk = cdiv(I, 256);
+  if (nchunk > 1024) nchunk = 1024;
+  uint32_t rows = cdiv(I, nchunk);
+  double* pv = c.d(c.SL->pv);
+  uint32_t* pi = (uint32_t*)(c.ws + c.SL->pi);
+  hipLaunchKernelGGL(k_colmax_partial, dim3(nchunk), dim3(256), 0, c.st, c.d(c.SL->Aw), I, R, rows, pv,
+                     pi, c.stat());
+  hipLaunchKernelGGL(k_sign_store, dim3(cdiv((uint64_t)I * 16, 256)), dim3(256), 0, c.st,
+                     c.d(c.SL->Aw), I, R, pv, pi, nchunk, Aout, af, c.stat());
+}
+
+}  // namespace
+
+hipError_t launch_solver_init(const SolverLayout& SL, char* ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_solver_init, dim3(1), dim3(64), 0, st, (int32_t*)(ws + SL.status),
+                     (int32_t*)(ws + SL.status + 16), 16);
+  return hipGetLastError();
+}
+
+hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k,
+                              double* A_out, const SampleHdr* hdr, hipStream_t st) {
+  (void)si;
+  Ctx c{&SL, ws, hdr, st};
+  const ModePlan& m = SL.mp[k];
+  hipError_t e = launch_gram_y(SL, ws, k, hdr, st);
+  if (e != hipSuccess) return e;
+  const double* G = c.d(SL.G);
+  int32_t tagval = 0x4d000000 | (k << 16) | (int32_t)m.s;
+  double* V;
+  uint32_t ldv;
+  if (m.s <= (uint32_t)kSmallEig) {
+    V = c.d(m.V);
+    ldv = m.s;
+    jacobi(c, G, m.s, V, c.d(m.lam), c.tags() + k, tagval, false);
+  } else {
+    V = c.d(m.Q64);
+    ldv = kBlock;
+    subspace_topk(c, G, m.s, m.R, V, c.d(m.lam), c.tags() + k, tagval, 24);
+  }
+  if (m.kside) {
+    uint32_t J = m.O * m.Q;
+    hipLaunchKernelGGL(k_backproject_dense, dim3(cdiv(m.I, 256)), dim3(256), 0, st,
+                       (const float*)(ws + m.ybuf), m.I, m.Q, J, make_fastdiv(m.Q), V, ldv,
+                       c.d(m.lam), m.R, c.d(SL.Aw), c.stat());
+    cholqr2(c, c.d(SL.Aw), 16, m.I, m.R, false);
+  } else {
+    hipLaunchKernelGGL(k_take_cols, dim3(cdiv((uint64_t)m.I * 16, 256)), dim3(256), 0, st, V, ldv,
+                       m.I, m.R, c.d(SL.Aw), c.stat());
+  }
+  sign_store(c, m.I, m.R, A_out, (float*)(ws + SL.af[k]));
+  return hipGetLastError();
+}
+
+hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
+                             char* ws, int n, int R, double* A_out, hipStream_t st) {
+  Ctx c{&SL, ws, sp.hdr, st};
+  hipError_t e = launch_gram_xhat(si, sp, SL, ws, n, st);
+  if (e != hipSuccess) return e;
+  const uint32_t s = SL.hosvd_s[n];
+  const double* G = c.d(SL.G);
+  double* V = c.d(SL.Qhs);
+  double* lam = c.d(SL.lamH) ;
+  uint32_t ldv;
+  int32_t* tagc = c.tags() + kTagCold;
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, tagc, 0);
+  if (s <= (uint32_t)kSmallEig) {
+    ldv = s;
+    jacobi(c, G, s, V, lam, tagc, 0x48000000 | (int32_t)s, false);
+  } else {
+    ldv = kBlock;
+    subspace_topk(c, G, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 80);
+  }
+  const uint32_t I = si.dims[n];
+  if (SL.hosvd_kside[n]) {
+    uint32_t J = si.N / I;
+    hipLaunchKernelGGL(k_backproject_xhat, dim3(cdiv(I, 256)), dim3(256), 0, st, sp.bitmap, sp.wrank,
+                       sp.coo_l, I, si.stride[n], J, si.fstride[n], V, ldv, lam, (uint32_t)R,
+                       c.d(SL.Aw), c.stat());
+    cholqr2(c, c.d(SL.Aw), 16, I, (uint32_t)R, false);
+  } else {
+    hipLaunchKernelGGL(k_take_cols, dim3(cdiv((uint64_t)I * 16, 256)), dim3(256), 0, st, V, ldv, I,
+                       (uint32_t)R, c.d(SL.Aw), c.stat());
+  }
+  sign_store(c, I, (uint32_t)R, A_out, (float*)(ws + SL.af[n]));
+  return hipGetLastError();
+}
+
+hipError_t launch_fit(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr, double* fit,
+                      hipStream_t st) {
+  const ModePlan& m = SL.mp[k];
+  hipLaunchKernelGGL(k_fit, dim3(1), dim3(64), 0, st, (const double*)(ws + m.lam), m.R, hdr,
+                     (const int32_t*)(ws + SL.status), fit, (double*)(ws + SL.status + 128));
+  return hipGetLastError();
+}
+
+hipError_t launch_core(const ShapeInfo& si, const SolverLayout& SL, char* ws, const double* A_last,
+                       double* G, double* norm2, const SampleHdr* hdr, hipStream_t st) {
+  const ModePlan& m = SL.mp[si.d - 1];
+  uint32_t n = m.O * m.Q * m.R;
+  const int32_t* stp = (const int32_t*)(ws + SL.status);
+  hipLaunchKernelGGL(k_core, dim3(cdiv(n, 256)), dim3(256), 0, st, (const float*)(ws + m.ybuf), m.O,
+                     m.I, m.Q, A_last, m.R, G, hdr, stp);
+  if (norm2)
+    hipLaunchKernelGGL(k_norm2, dim3(1), dim3(256), 0, st, G, n, norm2, hdr, stp);
+  return hipGetLastError();
+}
+
+}  // namespace mach

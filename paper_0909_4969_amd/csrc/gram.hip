@@ -1,0 +1,198 @@
+// Gram matrices of matricizations, on the smaller side (the leading left
+// singular vectors of a matrix M are the top eigenvectors of M M^T; when M
+// has fewer columns than rows, they are M v / sigma for the top
+// eigenvectors v of M^T M).
+//
+// A matricization M (rows i < I, columns j < J) of a C-order array with
+// "inner size" Q (the product of the dimensions after the row mode) puts
+// element (i, j) at  off(j) + i * Q,  off(j) = (j / Q) * I * Q + j mod Q.
+// This covers both the HOOI intermediates Y_k (view O x I_k x Q) and the
+// sampled tensor's unfolding Xhat_(n) (Q = stride of mode n).
+//   row side:    G[x, y] = sum_j M[x, j] M[y, j]   (I x I)
+//   column side: G[x, y] = sum_i M[i, x] M[i, y]   (J x J)
+// Products are float32, summed in float32 over 32 terms and then in
+// float64; each workgroup owns a 64x64 tile and a slice of the summation
+// range, and the slices are added in a fixed order.
+#include "solver.h"
+
+namespace mach {
+namespace {
+
+struct GramArgs {
+  uint32_t I, Q, J;       // matricization shape and inner size
+  FastDiv fQ;
+  int kside;              // 1: column side (J x J), 0: row side (I x I)
+  uint32_t X, Z;          // Gram side and summation length
+  uint32_t zchunk;        // summation slice per workgroup
+  double* part;           // [chunk][X][X]
+  const int32_t* st_solver;
+  const SampleHdr* hdr;
+};
+
+struct DenseLoad {
+  const float* base;
+  __device__ __forceinline__ float operator()(uint32_t l) const { return base[l]; }
+};
+
+// Xhat (unscaled) at linear index l: bitmap test, rank, kept value.
+struct MaskedLoad {
+  const uint64_t* bitmap;
+  const uint32_t* wrank;
+  const Entry* coo;
+  __device__ __forceinline__ float operator()(uint32_t l) const {
+    uint64_t word = bitmap[l >> 6];
+    uint32_t b = l & 63;
+    if (!((word >> b) & 1ull)) return 0.f;
+    uint64_t below = b ? (word & ((~0ull) >> (64 - b))) : 0ull;
+    return coo[wrank[l >> 6] + (uint32_t)__popcll(below)].v;
+  }
+};
+
+__device__ __forceinline__ uint32_t col_off(const GramArgs& a, uint32_t j) {
+  uint32_t q = a.fQ.div(j);
+  return q * a.I * a.Q + (j - q * a.Q);
+}
+
+template <typename Load>
+__global__ __launch_bounds__(256) void k_gram(GramArgs a, Load ld) {
+  if (a.hdr->status != 0 || *a.st_solver != 0) return;
+  __shared__ float Mx[32][65];
+  __shared__ float My[32][65];
+  const uint32_t x0 = blockIdx.x * 64, y0 = blockIdx.y * 64;
+  const uint32_t zc0 = blockIdx.z * a.zchunk;
+  const uint32_t zc1 = min(a.Z, zc0 + a.zchunk);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (uint32_t zs = zc0; zs < zc1; zs += 32) {
+    // stage 32 summation indices x 64 Gram indices for both tiles
+    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+      int zz = e >> 6, xx = e & 63;
+      uint32_t z = zs + zz;
+      float vx = 0.f, vy = 0.f;
+      if (z < zc1) {
+        uint32_t x = x0 + xx, y = y0 + xx;
+        if (a.kside) {
+          uint32_t zo = z * a.Q;
+          if (x < a.X) vx = ld(zo + col_off(a, x));
+          if (y < a.X) vy = ld(zo + col_off(a, y));
+        } else {
+          uint32_t zo = col_off(a, z);
+          if (x < a.X) vx = ld(zo + x * a.Q);
+          if (y < a.X) vy = ld(zo + y * a.Q);
+        }
+      }
+      Mx[zz][xx] = vx;
+      My[zz][xx] = vy;
+    }
+    __syncthreads();
+    float c[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c[i][j] = 0.f;
+#pragma unroll 8
+    for (int zz = 0; zz < 32; ++zz) {
+      float u[4], w[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        u[i] = Mx[zz][tx * 4 + i];
+        w[i] = My[zz][ty * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[i][j] = fmaf(u[i], w[j], c[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += (double)c[i][j];
+    __syncthreads();
+  }
+  double* out = a.part + (size_t)blockIdx.z * a.X * a.X;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t x = x0 + tx * 4 + i, y = y0 + ty * 4 + j;
+      if (x < a.X && y < a.X) out[(size_t)x * a.X + y] = acc[i][j];
+    }
+}
+
+// G = sum over chunks of part (fixed order).
+__global__ void k_gram_reduce(const double* __restrict__ part, uint32_t nchunk, uint32_t n2,
+                              double* __restrict__ G, const SampleHdr* hdr, const int32_t* st_solver) {
+  if (hdr->status != 0 || *st_solver != 0) return;
+  uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n2) return;
+  double s = 0.0;
+  for (uint32_t c = 0; c < nchunk; ++c) s += part[(size_t)c * n2 + e];
+  G[e] = s;
+}
+
+template <typename Load>
+hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream_t st) {
+  uint32_t tiles = (a.X + 63) / 64;
+  uint64_t n2 = (uint64_t)a.X * a.X;
+  // Slices of at least 256 summation indices; enough workgroups to fill
+  // the chip; the partials must fit their buffer.
+  uint32_t nchunk = 1;
+  while (nchunk < 1024 && (uint64_t)tiles * tiles * nchunk < 512 &&
+         a.Z / (2 * nchunk) >= 256 && n2 * (2 * nchunk) <= part_elems)
+    nchunk *= 2;
+  a.zchunk = (a.Z + nchunk - 1) / nchunk;
+  a.zchunk = (a.zchunk + 31) / 32 * 32;
+  nchunk = (a.Z + a.zchunk - 1) / a.zchunk;
+  if (nchunk < 1) nchunk = 1;
+  if (nchunk == 1) a.part = G;
+  hipLaunchKernelGGL((k_gram<Load>), dim3(tiles, tiles, nchunk), dim3(256), 0, st, a, ld);
+  if (nchunk > 1)
+    hipLaunchKernelGGL(k_gram_reduce, dim3((uint32_t)((n2 + 255) / 256)), dim3(256), 0, st, a.part,
+                       nchunk, (uint32_t)n2, G, a.hdr, a.st_solver);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Gram of Y_k (dense float32 view) into SL.G.
+hipError_t launch_gram_y(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
+                         hipStream_t st) {
+  const ModePlan& m = SL.mp[k];
+  GramArgs a{};
+  a.I = m.I;
+  a.Q = m.Q;
+  a.J = m.O * m.Q;
+  a.fQ = make_fastdiv(m.Q);
+  a.kside = m.kside;
+  a.X = m.s;
+  a.Z = m.kside ? m.I : a.J;
+  a.part = (double*)(ws + SL.Gpart);
+  a.st_solver = (const int32_t*)(ws + SL.status);
+  a.hdr = hdr;
+  DenseLoad ld{(const float*)(ws + m.ybuf)};
+  return gram_run(a, ld, (double*)(ws + SL.G), SL.Gpart_elems, st);
+}
+
+// Gram of the sampled unfolding Xhat_(n) (unscaled values) into SL.G.
+hipError_t launch_gram_xhat(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
+                            char* ws, int n, hipStream_t st) {
+  GramArgs a{};
+  a.I = si.dims[n];
+  a.Q = si.stride[n];
+  a.J = si.N / si.dims[n];
+  a.fQ = si.fstride[n];
+  a.kside = SL.hosvd_kside[n];
+  a.X = SL.hosvd_s[n];
+  a.Z = a.kside ? a.I : a.J;
+  a.part = (double*)(ws + SL.Gpart);
+  a.st_solver = (const int32_t*)(ws + SL.status);
+  a.hdr = sp.hdr;
+  MaskedLoad ld{sp.bitmap, sp.wrank, sp.coo_l};
+  return gram_run(a, ld, (double*)(ws + SL.G), SL.Gpart_elems, st);
+}
+
+}  // namespace mach

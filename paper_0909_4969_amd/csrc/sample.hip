@@ -1,0 +1,352 @@
+// MACH coin toss (Alg. 1/2, "MACH" block; Theorem 1; Remark 1) and the
+// sparse layouts built from it.
+//
+// Pipeline (all on one stream, no host synchronisation):
+//   init      header fields (p, threshold, capacity, seed, window)
+//   mask      Philox4x32-10 word per linear index -> keep bitmap, one 64-bit
+//             word per thread, and a kept count per 16384-entry block
+//   scan      exclusive scan of the block counts (one workgroup)
+//   compact   per block: word ranks, then every kept entry written as
+//             (l, float32 x_l) at its rank, plus sum x^2 in float64
+//   finalize  kept count, sum x^2 (fixed-order tree), capacity status
+//   rowptr    CSR row pointers = rank of each head row's first index
+//   headrow   head row index of each position in the CSC head order
+//   csc_count / scan / csc_fill   the CSC copy: for every tail column c,
+//             its kept entries ordered by the head coordinates in headperm
+//             order.  A column is read by 64 lanes at once (64 consecutive c
+//             share bitmap words), so no sort is needed.
+#include <cmath>
+
+#include "mach_internal.h"
+
+namespace mach {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Block-wide sum over 256 threads in a fixed order; result valid in thread 0.
+template <typename T>
+__device__ __forceinline__ T block_sum256(T v, T* sh) {
+  v = wave_sum(v);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T r = 0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// Exclusive scan over 256 threads; returns the exclusive prefix, total in *tot.
+__device__ __forceinline__ uint32_t block_exscan256(uint32_t v, uint32_t* sh, uint32_t* tot) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int i = 0; i < w; ++i) base += sh[i];
+  *tot = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return base + x - v;
+}
+
+__global__ void k_sample_init(SampleHdr* hdr, double p, uint64_t thresh, uint64_t cap,
+                              uint64_t seed, uint64_t window) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    hdr->nnz = 0;
+    hdr->cap = cap;
+    hdr->p = p;
+    hdr->sumsq = 0.0;
+    hdr->thresh = thresh;
+    hdr->seed = seed;
+    hdr->window = window;
+    hdr->status = 0;
+    hdr->magic = kSampleMagic;
+  }
+}
+
+// One thread per 64-bit bitmap word: 16 Philox blocks, 4 words each.
+__global__ __launch_bounds__(kThreads) void k_sample_mask(uint32_t N, uint64_t thresh, uint32_t s_lo,
+                                                          uint32_t s_hi, uint32_t w_lo, uint32_t w_hi,
+                                                          uint64_t* __restrict__ bitmap,
+                                                          uint32_t* __restrict__ blkcnt) {
+  __shared__ uint32_t sh[4];
+  uint32_t w = blockIdx.x * kSampleBlockWords + threadIdx.x;
+  uint64_t bits = 0;
+  uint32_t l0 = w * 64u;
+  if (l0 < N) {
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+      uint32_t c[4] = {w * 16u + (uint32_t)j, 0u, w_lo, w_hi};
+      philox4x32_10(c, s_lo, s_hi);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        uint32_t l = l0 + 4u * j + k;
+        uint64_t keep = ((uint64_t)c[k] < thresh) && (l < N);
+        bits |= keep << (4 * j + k);
+      }
+    }
+  }
+  bitmap[w] = bits;
+  uint32_t tot = block_sum256<uint32_t>((uint32_t)__popcll(bits), sh);
+  if (threadIdx.x == 0) blkcnt[blockIdx.x] = tot;
+}
+
+// Single-workgroup exclusive scan in place over a[0..n); a[n] receives the total.
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, uint32_t n) {
+  __shared__ uint32_t part[1024];
+  uint32_t t = threadIdx.x;
+  uint32_t chunk = (n + 1023) / 1024;
+  uint32_t b = t * chunk, e = min(n, b + chunk);
+  uint32_t s = 0;
+  for (uint32_t i = b; i < e; ++i) s += a[i];
+  part[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over 1024 partials.
+  for (uint32_t o = 1; o < 1024; o <<= 1) {
+    uint32_t y = t >= o ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += y;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;
+  for (uint32_t i = b; i < e; ++i) {
+    uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  if (t == 1023) a[n] = part[1023];
+}
+
+// Four consecutive inputs at a 4-element-aligned index (the tensor base is
+// at least 16-byte aligned): one 16-byte load for float, two for double.
+__device__ __forceinline__ void load4(const float* p, float x[4]) {
+  float4 v = *reinterpret_cast<const float4*>(p);
+  x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* p, double x[4]) {
+  double2 a = reinterpret_cast<const double2*>(p)[0];
+  double2 b = reinterpret_cast<const double2*>(p)[1];
+  x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
+}
+
+template <typename XT>
+__global__ __launch_bounds__(kThreads) void k_sample_compact(const XT* __restrict__ X, uint32_t N,
+                                                             const uint64_t* __restrict__ bitmap,
+                                                             const uint32_t* __restrict__ blkoff,
+                                                             uint32_t* __restrict__ wrank,
+                                                             Entry* __restrict__ coo, uint64_t cap,
+                                                             double* __restrict__ sumsq_part) {
+  __shared__ uint64_t words[kSampleBlockWords];
+  __shared__ uint32_t lrank[kSampleBlockWords];
+  __shared__ uint32_t sh[4];
+  __shared__ double shd[4];
+  const uint32_t b = blockIdx.x;
+  const uint32_t base_word = b * kSampleBlockWords;
+  const uint64_t myword = bitmap[base_word + threadIdx.x];
+  uint32_t tot;
+  uint32_t ex = block_exscan256((uint32_t)__popcll(myword), sh, &tot);
+  const uint32_t off = blkoff[b];
+  wrank[base_word + threadIdx.x] = off + ex;
+  words[threadIdx.x] = myword;
+  lrank[threadIdx.x] = ex;
+  __syncthreads();
+  double ss = 0.0;
+  const uint32_t base_elem = b * kSampleBlockElems;
+  for (int it = 0; it < 16; ++it) {
+    uint32_t g = it * kThreads + threadIdx.x;
+    uint32_t e0 = base_elem + 4u * g;
+    uint32_t wi = g >> 4, sh4 = (g & 15u) * 4u;
+    uint64_t word = words[wi];
+    uint32_t nib = (uint32_t)(word >> sh4) & 15u;
+    if (nib == 0) continue;
+    uint64_t below = sh4 ? (word & ((~0ull) >> (64 - sh4))) : 0ull;
+    uint64_t r = (uint64_t)off + lrank[wi] + (uint32_t)__popcll(below);
+    XT x[4];
+    if (e0 + 3 < N) {
+      load4(X + e0, x);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = (e0 + k < N) ? X[e0 + k] : (XT)0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if ((nib >> k) & 1u) {
+        double xv = (double)x[k];
+        if (r < cap) {
+          Entry en;
+          en.l = e0 + k;
+          en.v = (float)x[k];
+          coo[r] = en;
+        }
+        ss += xv * xv;
+        ++r;
+      }
+    }
+  }
+  double s = block_sum256<double>(ss, shd);
+  if (threadIdx.x == 0) sumsq_part[b] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sample_finalize(SampleHdr* hdr, const uint32_t* blkoff,
+                                                         uint32_t nblk, const double* sumsq_part,
+                                                         uint32_t* wrank, uint32_t nwords) {
+  __shared__ double shd[4];
+  double s = 0.0;
+  for (uint32_t i = threadIdx.x; i < nblk; i += 256) s += sumsq_part[i];
+  s = block_sum256<double>(s, shd);
+  if (threadIdx.x == 0) {
+    uint64_t nnz = blkoff[nblk];
+    hdr->nnz = nnz;
+    hdr->sumsq = s;
+    wrank[nwords] = (uint32_t)nnz;
+    if (nnz > hdr->cap) hdr->status = MACH_ENOMEM;
+  }
+}
+
+__global__ void k_rowptr(ShapeInfo si, const uint64_t* __restrict__ bitmap,
+                         const uint32_t* __restrict__ wrank, const SampleHdr* hdr,
+                         uint32_t* __restrict__ rowptr) {
+  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > si.MH) return;
+  uint64_t cap = hdr->cap;
+  uint64_t v = (r == si.MH) ? hdr->nnz : (uint64_t)bit_rank(bitmap, wrank, r * si.MT);
+  rowptr[r] = (uint32_t)(v < cap ? v : cap);
+}
+
+// headrow[t] = C-order head row index of position t in headperm order.
+__global__ void k_headrow(ShapeInfo si, uint32_t* __restrict__ headrow) {
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= si.MH) return;
+  uint32_t rem = t, r = 0;
+  for (int j = si.h - 1; j >= 0; --j) {
+    int m = si.headperm[j];
+    uint32_t i = si.fdim[m].mod(rem);
+    rem = si.fdim[m].div(rem);
+    r += i * (si.stride[m] / si.MT);
+  }
+  headrow[t] = r;
+}
+
+// Wave = (64 consecutive tail columns) x (one block of rb head rows).
+__global__ __launch_bounds__(256) void k_csc_count(ShapeInfo si, const uint64_t* __restrict__ bitmap,
+                                                   const uint32_t* __restrict__ headrow,
+                                                   uint32_t* __restrict__ cnt) {
+  uint32_t rb = blockIdx.y * 4 + (threadIdx.x >> 6);
+  uint32_t c = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (rb >= si.nrb || c >= si.MT) return;
+  uint32_t t0 = rb * si.rb, t1 = min(si.MH, t0 + si.rb);
+  uint32_t n = 0;
+  for (uint32_t t = t0; t < t1; ++t) {
+    uint32_t l = headrow[t] * si.MT + c;
+    n += (uint32_t)(bitmap[l >> 6] >> (l & 63)) & 1u;
+  }
+  cnt[c * si.nrb + rb] = n;
+}
+
+__global__ __launch_bounds__(256) void k_csc_fill(ShapeInfo si, const uint64_t* __restrict__ bitmap,
+                                                  const uint32_t* __restrict__ wrank,
+                                                  const uint32_t* __restrict__ headrow,
+                                                  const uint32_t* __restrict__ cnt,
+                                                  const Entry* __restrict__ coo_l,
+                                                  Entry* __restrict__ coo_t, uint32_t* __restrict__ colptr,
+                                                  const SampleHdr* hdr) {
+  uint32_t rb = blockIdx.y * 4 + (threadIdx.x >> 6);
+  uint32_t c = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (rb >= si.nrb || c >= si.MT) return;
+  const uint64_t cap = hdr->cap;
+  uint64_t dest = cnt[c * si.nrb + rb];
+  if (rb == 0) colptr[c] = (uint32_t)(dest < cap ? dest : cap);
+  if (rb == 0 && c == 0) {
+    uint64_t nnz = hdr->nnz;
+    colptr[si.MT] = (uint32_t)(nnz < cap ? nnz : cap);
+  }
+  uint32_t t0 = rb * si.rb, t1 = min(si.MH, t0 + si.rb);
+  for (uint32_t t = t0; t < t1; ++t) {
+    uint32_t l = headrow[t] * si.MT + c;
+    uint64_t word = bitmap[l >> 6];
+    uint32_t b = l & 63;
+    if ((word >> b) & 1ull) {
+      uint64_t below = b ? (word & ((~0ull) >> (64 - b))) : 0ull;
+      uint64_t src = (uint64_t)wrank[l >> 6] + (uint32_t)__popcll(below);
+      if (src < cap && dest < cap) coo_t[dest] = coo_l[src];
+      ++dest;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, double p, uint64_t seed,
+                         uint64_t window, char* ws, const SampleLayout& L, uint64_t cap,
+                         hipStream_t st) {
+  SampleHdr* hdr = (SampleHdr*)(ws + L.hdr);
+  uint64_t* bitmap = (uint64_t*)(ws + L.bitmap);
+  uint32_t* wrank = (uint32_t*)(ws + L.wrank);
+  uint32_t* blkcnt = (uint32_t*)(ws + L.blkcnt);
+  double* sumsq_part = (double*)(ws + L.sumsq_part);
+  Entry* coo_l = (Entry*)(ws + L.coo_l);
+  uint32_t* rowptr = (uint32_t*)(ws + L.rowptr);
+  uint32_t* colptr = (uint32_t*)(ws + L.colptr);
+  uint32_t* csc_cnt = (uint32_t*)(ws + L.csc_cnt);
+  uint32_t* headrow = (uint32_t*)(ws + L.headrow);
+  Entry* coo_t = (Entry*)(ws + L.coo_t);
+
+  uint64_t thresh = (uint64_t)std::floor(p * 4294967296.0);
+  if (thresh > (1ull << 32)) thresh = 1ull << 32;
+
+  hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, hdr, p, thresh, cap, seed, window);
+  hipLaunchKernelGGL(k_sample_mask, dim3(si.nblk), dim3(kThreads), 0, st, si.N, thresh,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)window,
+                     (uint32_t)(window >> 32), bitmap, blkcnt);
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, blkcnt, si.nblk);
+  if (x_is_f64)
+    hipLaunchKernelGGL(k_sample_compact<double>, dim3(si.nblk), dim3(kThreads), 0, st,
+                       (const double*)X, si.N, bitmap, blkcnt, wrank, coo_l, cap, sumsq_part);
+  else
+    hipLaunchKernelGGL(k_sample_compact<float>, dim3(si.nblk), dim3(kThreads), 0, st,
+                       (const float*)X, si.N, bitmap, blkcnt, wrank, coo_l, cap, sumsq_part);
+  hipLaunchKernelGGL(k_sample_finalize, dim3(1), dim3(256), 0, st, hdr, blkcnt, si.nblk,
+                     sumsq_part, wrank, si.nwords);
+  hipLaunchKernelGGL(k_rowptr, dim3((si.MH + 1 + 255) / 256), dim3(256), 0, st, si, bitmap,
+                     wrank, hdr, rowptr);
+  hipLaunchKernelGGL(k_headrow, dim3((si.MH + 255) / 256), dim3(256), 0, st, si, headrow);
+  dim3 g((si.MT + 63) / 64, (si.nrb + 3) / 4);
+  hipLaunchKernelGGL(k_csc_count, g, dim3(256), 0, st, si, bitmap, headrow, csc_cnt);
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, csc_cnt, si.MT * si.nrb);
+  hipLaunchKernelGGL(k_csc_fill, g, dim3(256), 0, st, si, bitmap, wrank, headrow, csc_cnt, coo_l,
+                     coo_t, colptr, hdr);
+  return hipGetLastError();
+}
+
+}  // namespace mach

@@ -1,0 +1,102 @@
+// Solver-side internals: the per-mode tensor views of a HOOI sweep, the
+// solver workspace layout and the kernel launchers.
+//
+// A sweep splits the modes into head modes 0..h-1 and tail modes h..d-1
+// (ShapeInfo).  Two sparse passes per sweep serve all d mode updates:
+//   TH = Xhat x_{k >= h} A_k^T   (MH x KT, from the CSR copy; KT = prod_{k>=h} R_k)
+//   TT = Xhat x_{k <  h} A_k^T   (MT x KH, from the CSC copy; KH = prod_{k<h} R_k)
+// TH is formed before the head updates and TT after them, so each Y below
+// uses the factors Alg. 2 prescribes (modes updated in order 1..d).  Mode
+// products along different modes commute (Section 2.1), so
+//   Y_k = TH x_{j in head, j != k} A_j^T   for a head mode k,
+//   Y_k = TT x_{j in tail, j != k} A_j^T   for a tail mode k,
+// which is the tensor of Alg. 2's "Y <-" line with rows permuted.
+#pragma once
+
+#include "mach_internal.h"
+
+namespace mach {
+
+// Y_k viewed as a 3-way array (O, I_k, Q), element (o, i, q) at
+// (o * I_k + i) * Q + q; the matricization Y_(k) is I_k x (O*Q).
+struct YView {
+  const float* base;
+  uint32_t O, I, Q;
+};
+
+struct ModePlan {
+  uint32_t I, R, K;        // I_k, R_k, K_k = prod_{j != k} R_j
+  uint32_t s;              // Gram side = min(I, K)
+  int kside;               // 1: Gram is Y^T Y (K x K); 0: Y Y^T (I x I)
+  // dense contraction that forms Y_k from TH/TT (contract == -1: none)
+  int contract_mode;       // mode whose factor is applied
+  uint32_t cO, cI, cQ;     // view of the source for that contraction
+  uint32_t O, Q;           // view of Y_k
+  size_t ybuf;             // byte offset of Y_k's buffer (or of TH/TT)
+  size_t V, lam, Q64;      // eigen state: V (s x s) or Q64 (s x kBlock)
+};
+
+constexpr uint32_t kBlock = 64;          // subspace block for sides > kSmallEig
+
+// Status region: int32 status word at +0, int32 tags[16] at +16 (eigen
+// warm-start tags of modes 0..7, then kTagRR, kTagCold, kTagDone), doubles
+// from +128.
+constexpr int kTagRR = 8, kTagCold = 9, kTagDone = 10;
+
+struct SolverLayout {
+  size_t status;                         // see above
+  size_t af[kMaxD];                      // float32 factors, I_k x 16
+  size_t TH, TT;
+  size_t G, Gpart, Gpart_elems;          // float64 Gram and its partials
+  size_t Aw;                             // float64 I_max x 16 scratch
+  uint32_t zrows;                        // rows of the subspace scratch blocks
+  size_t Zs, Z2s, Qrs, Qhs;              // float64 zrows x 64 each
+  size_t H, VH, lamH, small;             // float64 64 x 64 (lamH: 64)
+  size_t part;                           // float64 64 x 64 x 64 partials
+  size_t pv, pi;                         // column-max partials (1024 x 16)
+  size_t total;
+  ModePlan mp[kMaxD];
+  uint32_t KT, KH, hosvd_s[kMaxD];
+  int hosvd_kside[kMaxD];
+};
+
+bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout* out);
+
+struct SparsePtrs {
+  const SampleHdr* hdr;
+  const uint64_t* bitmap;
+  const uint32_t* wrank;
+  const Entry* coo_l;
+  const Entry* coo_t;
+  const uint32_t* rowptr;
+  const uint32_t* colptr;
+  const uint32_t* csc_cnt;
+};
+
+SparsePtrs sparse_ptrs(const char* ws_sample, const SampleLayout& L);
+
+// ---- launchers -------------------------------------------------------------
+// Sparse passes (ttm.hip).  density = nnz_cap / N, used only to pick the
+// number of lanes per segment.
+hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
+                                char* ws, const int32_t* ranks, double density, hipStream_t st);
+hipError_t launch_contract_head(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
+                                char* ws, const int32_t* ranks, double density, hipStream_t st);
+hipError_t launch_form_y(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k,
+                         const SampleHdr* hdr, hipStream_t st);
+hipError_t launch_factors_to_f32(const ShapeInfo& si, const SolverLayout& SL, char* ws,
+                                 double* const* A, const int32_t* ranks, const SampleHdr* hdr,
+                                 hipStream_t st);
+
+// Gram, eigensolve and factor update of one mode from Y_k (gram.hip, eig.hip).
+hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k,
+                              double* A_out, const SampleHdr* hdr, hipStream_t st);
+hipError_t launch_fit(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr, double* fit,
+                      hipStream_t st);
+hipError_t launch_core(const ShapeInfo& si, const SolverLayout& SL, char* ws, const double* A_last,
+                       double* G, double* norm2, const SampleHdr* hdr, hipStream_t st);
+hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
+                             char* ws, int n, int R, double* A_out, hipStream_t st);
+hipError_t launch_solver_init(const SolverLayout& SL, char* ws, hipStream_t st);
+
+}  // namespace mach
