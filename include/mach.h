@@ -175,6 +175,16 @@ mach_status mach_sample_offsets(const mach_shape* s, uint64_t nnz_cap, uint64_t*
 mach_status mach_read_status(const void* ws_sample, const void* ws_solver, void* stream,
                              int32_t* status_out, uint64_t* nnz_out, double* sumsq_out);
 
+/* Kernel timing for measurement tools.  While enabled, every sparse
+ * tensor-times-matrix pass is launched with a start/stop event pair that
+ * brackets exactly its dispatch; mach_timing_enable(1) also clears the
+ * record.  mach_timing_read waits for the recorded events of one pass kind
+ * (which = 0: the pass over head rows, 1: the pass over tail columns) and
+ * returns their summed duration in milliseconds and their number.  Events
+ * are created once and reused (no device memory).  Not thread safe. */
+mach_status mach_timing_enable(int32_t on);
+mach_status mach_timing_read(int32_t which, double* total_ms, int32_t* count);
+
 /* Static description of a status code. */
 const char* mach_status_string(mach_status st);
 

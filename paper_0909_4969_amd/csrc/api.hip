@@ -90,6 +90,7 @@ SampleLayout sample_layout(const ShapeInfo& si, uint64_t cap) {
   L.csc_cnt = take(((size_t)si.MT * si.nrb + 1) * 4);
   L.headrow = take((size_t)si.MH * 4);
   L.coo_t = take((size_t)cap * 8);
+  L.scan_tmp = take(((size_t)si.MT * si.nrb / 4096 + si.nblk / 4096 + 2) * 4);
   L.total = o;
   return L;
 }
@@ -213,6 +214,7 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
     m.kside = m.K < m.I;
     m.s = m.kside ? m.K : m.I;
     if (m.R > m.s) return false;
+    if (m.kside && m.I > 262144) return false;
     m.contract_mode = -1;
     if (m.s > smax_sweep) smax_sweep = m.s;
     if (m.s > (uint32_t)kSmallEig && m.s > zrows) zrows = m.s;
@@ -312,6 +314,37 @@ SparsePtrs sparse_ptrs(const char* ws, const SampleLayout& L) {
   p.colptr = (const uint32_t*)(ws + L.colptr);
   p.csc_cnt = (const uint32_t*)(ws + L.csc_cnt);
   return p;
+}
+
+namespace {
+
+// Kernel timing hook state (host side, not thread safe).
+struct TimingPool {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
+  size_t used[2] = {0, 0};
+};
+TimingPool g_timing;
+
+}  // namespace
+
+bool timing_events(int which, hipEvent_t* e0, hipEvent_t* e1) {
+  if (!g_timing.on || which < 0 || which > 1) return false;
+  auto& v = g_timing.ev[which];
+  size_t& u = g_timing.used[which];
+  if (u == v.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return false;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return false;
+    }
+    v.push_back({a, b});
+  }
+  *e0 = v[u].first;
+  *e1 = v[u].second;
+  ++u;
+  return true;
 }
 
 namespace {
@@ -432,6 +465,27 @@ mach_status mach_core(const void* ws_sample, uint64_t nnz_cap, const mach_shape*
   return ok ? MACH_OK : MACH_EDEVICE;
 }
 
+mach_status mach_timing_enable(int32_t on) {
+  g_timing.on = on != 0;
+  g_timing.used[0] = g_timing.used[1] = 0;
+  return MACH_OK;
+}
+
+mach_status mach_timing_read(int32_t which, double* total_ms, int32_t* count) {
+  if (which < 0 || which > 1 || !total_ms || !count) return MACH_EINVAL;
+  double tot = 0.0;
+  for (size_t i = 0; i < g_timing.used[which]; ++i) {
+    auto& pr = g_timing.ev[which][i];
+    if (hipEventSynchronize(pr.second) != hipSuccess) return MACH_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) return MACH_EDEVICE;
+    tot += ms;
+  }
+  *total_ms = tot;
+  *count = (int32_t)g_timing.used[which];
+  return MACH_OK;
+}
+
 int32_t mach_host_selftest(void) {
   // 1. fast division against the hardware divide
   uint64_t x = 88172645463325252ull;
@@ -485,7 +539,7 @@ int32_t mach_host_selftest(void) {
   if (si.headperm[0] != 1 || si.headperm[1] != 0) return 6;
   SampleLayout L = sample_layout(si, 3500000);
   size_t offs[] = {L.hdr, L.bitmap, L.wrank, L.blkcnt, L.sumsq_part, L.coo_l, L.rowptr,
-                   L.colptr, L.csc_cnt, L.headrow, L.coo_t, L.total};
+                   L.colptr, L.csc_cnt, L.headrow, L.coo_t, L.scan_tmp, L.total};
   for (size_t i = 0; i + 1 < sizeof(offs) / sizeof(offs[0]); ++i)
     if ((offs[i] & 255) || offs[i + 1] <= offs[i]) return 7;
   int32_t r3[] = {8, 4, 16};

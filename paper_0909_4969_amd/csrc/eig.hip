@@ -26,12 +26,18 @@ namespace mach {
 
 hipError_t launch_gram_y(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
                          hipStream_t st);
+hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
+                                  hipStream_t st, uint32_t* nchunk);
 hipError_t launch_gram_xhat(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
                             char* ws, int n, hipStream_t st);
 
 namespace {
 
 constexpr int kMaxSweeps = 40;
+// Jacobi stops when the off-diagonal Frobenius norm is below 1e-10 of the
+// diagonal's: eigenvector errors are then below 1e-10 / (relative gap),
+// far under the float32 rounding of the Gram that feeds the solve.
+constexpr double kOffTol2 = 1e-20;
 
 __device__ __forceinline__ void jpair(int r, int k, int np, int* p, int* q) {
   int m = np - 1, a, b;
@@ -82,128 +88,428 @@ struct JacArgs {
   Status s;
 };
 
-__global__ __launch_bounds__(256) void k_jacobi_small(JacArgs a) {
-  if (a.s.skip()) return;
-  __shared__ double A[64][65];
-  __shared__ double B[64][65];
-  __shared__ double C[64][65];
-  __shared__ double rc[32], rs[32], rt[32];
-  __shared__ int rp[32], rq[32], rk[64];
-  __shared__ double red[2][4];
-  const int n = (int)a.n, np = (n + 1) & ~1, tid = threadIdx.x;
-  const bool warm = (*a.tag == a.tagval);
-  for (int e = tid; e < np * np; e += 256) {
-    int x = e / np, y = e % np;
-    A[x][y] = (x < n && y < n) ? a.G[x * n + y] : 0.0;
-    B[x][y] = (warm && x < n && y < n) ? a.V[x * n + y] : (x == y ? 1.0 : 0.0);
+// LDS state of the Jacobi kernels for a padded size NP (power of two).
+template <int NP>
+struct JacLds {
+  double A[2][NP][NP + 1];              // double-buffered matrix
+  double V[NP][NP + 1];                 // accumulated rotations
+  unsigned char tp[NP - 1][NP / 2], tq[NP - 1][NP / 2];
+  int rk[NP];
+  double red[2][4];
+};
+
+// Loads V (warm start, n x n row-major) or the identity into L.V and, when
+// warm, replaces L.A[0] = G by V^T G V.  Expects L.A[0] = G (padded).
+template <int NP>
+__device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NP * NP; e += 256) {
+    int x = e / NP, y = e % NP;
+    L.V[x][y] = (warm && x < n && y < n) ? Vin[x * n + y] : (x == y ? 1.0 : 0.0);
+  }
+  for (int e = tid; e < (NP - 1) * (NP / 2); e += 256) {
+    int r = e / (NP / 2), k = e % (NP / 2), p, q;
+    jpair(r, k, NP, &p, &q);
+    L.tp[r][k] = (unsigned char)p;
+    L.tq[r][k] = (unsigned char)q;
   }
   __syncthreads();
-  if (warm) {
-    for (int e = tid; e < np * np; e += 256) {
-      int x = e / np, y = e % np;
-      double s = 0.0;
-      for (int z = 0; z < np; ++z) s = fma(A[x][z], B[z][y], s);
-      C[x][y] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < np * np; e += 256) {
-      int x = e / np, y = e % np;
-      double s = 0.0;
-      for (int z = 0; z < np; ++z) s = fma(B[z][x], C[z][y], s);
-      A[x][y] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < np * np; e += 256) {
-      int x = e / np, y = e % np;
-      if (x < y) {
-        double m = 0.5 * (A[x][y] + A[y][x]);
-        A[x][y] = m;
-        A[y][x] = m;
+  if (!warm) return;
+  // A[1] = G V, then A[0] = V^T A[1]; 4x4 register blocks per thread.
+  const int bx = (tid / (NP / 4)) * 4, by = (tid % (NP / 4)) * 4;
+  const bool own = tid < (NP / 4) * (NP / 4);
+  double acc[4][4];
+  if (own) {
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int z = 0; z < n; ++z) {
+      double u[4], w[4];
+      for (int i = 0; i < 4; ++i) {
+        u[i] = L.A[0][bx + i][z];
+        w[i] = L.V[z][by + i];
       }
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
     }
-    __syncthreads();
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) L.A[1][bx + i][by + j] = acc[i][j];
   }
-  const int npairs = np / 2;
-  bool conv = false;
+  __syncthreads();
+  if (own) {
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int z = 0; z < n; ++z) {
+      double u[4], w[4];
+      for (int i = 0; i < 4; ++i) {
+        u[i] = L.V[z][bx + i];
+        w[i] = L.A[1][z][by + i];
+      }
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
+    }
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) L.A[0][bx + i][by + j] = acc[i][j];
+  }
+  __syncthreads();
+  for (int e = tid; e < NP * NP; e += 256) {
+    int x = e / NP, y = e % NP;
+    if (x < y) {
+      double m = 0.5 * (L.A[0][x][y] + L.A[0][y][x]);
+      L.A[0][x][y] = m;
+      L.A[0][y][x] = m;
+    }
+  }
+  __syncthreads();
+}
+
+// Cyclic two-sided Jacobi on L.A[0] (n x n padded to NP, symmetric),
+// accumulating rotations into L.V.  Each round applies NP/2 disjoint
+// rotations (round-robin ordering): every wave computes the round's
+// rotations in its lanes and hands them out by shuffles; every 2x2 block
+// is read from one buffer and written to the other, so a round needs a
+// single barrier.  A rotation is skipped when |a_pq| <= 1e-17 (|a_pp| +
+// |a_qq|); a round with no rotation left is skipped as a whole.  Stops
+// when sum_{p != q} a_pq^2 <= 1e-26 sum_p a_pp^2.  Returns the index of
+// the buffer holding the result; *conv tells whether it converged.
+template <int NP>
+__device__ int jacobi_core(JacLds<NP>& L, bool* conv, int* sweeps_used = nullptr) {
+  constexpr int PAIRS = NP / 2, ROUNDS = NP - 1;
+  constexpr int BITER = (PAIRS * PAIRS + 255) / 256, VITER = (NP * PAIRS + 255) / 256;
+  const int tid = threadIdx.x, lane = tid & 63;
+  int cur = 0;
+  *conv = false;
   for (int sweep = 0; sweep <= kMaxSweeps; ++sweep) {
     double off = 0.0, dg = 0.0;
-    for (int e = tid; e < np * np; e += 256) {
-      int x = e / np, y = e % np;
-      double v = A[x][y];
+    for (int e = tid; e < NP * NP; e += 256) {
+      int x = e / NP, y = e % NP;
+      double v = L.A[cur][x][y];
       if (x == y) dg += v * v;
       else off += v * v;
     }
-    block_sum2(off, dg, red);
-    conv = (off <= 1e-26 * dg) || dg == 0.0;
-    if (conv || sweep == kMaxSweeps) break;
-    for (int r = 0; r < np - 1; ++r) {
-      if (tid < npairs) {
-        int p, q;
-        jpair(r, tid, np, &p, &q);
-        double apq = A[p][q], app = A[p][p], aqq = A[q][q];
-        double c = 1.0, s = 0.0, t = 0.0;
-        if (fabs(apq) > 1e-300) {
+    block_sum2(off, dg, L.red);
+    *conv = (off <= kOffTol2 * dg) || dg == 0.0;
+    if (sweeps_used) *sweeps_used = sweep;
+    if (*conv || sweep == kMaxSweeps) break;
+    for (int r = 0; r < ROUNDS; ++r) {
+      double c = 1.0, sn = 0.0, t = 0.0;
+      int act = 0;
+      if (lane < PAIRS) {
+        int p = L.tp[r][lane], q = L.tq[r][lane];
+        double apq = L.A[cur][p][q], app = L.A[cur][p][p], aqq = L.A[cur][q][q];
+        if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * (fabs(app) + fabs(aqq))) {
           double th = (aqq - app) / (2.0 * apq);
-          t = fabs(th) > 1e150 ? 0.5 / th : copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
-        }
-        rc[tid] = c;
-        rs[tid] = s;
-        rt[tid] = t;
-        rp[tid] = p;
-        rq[tid] = q;
-      }
-      __syncthreads();
-      for (int blk = tid; blk < npairs * npairs; blk += 256) {
-        int ia = blk / npairs, ib = blk % npairs;
-        int pa = rp[ia], qa = rq[ia], pb = rp[ib], qb = rq[ib];
-        if (ia == ib) {
-          double t = rt[ia], apq = A[pa][qa];
-          A[pa][pa] -= t * apq;
-          A[qa][qa] += t * apq;
-          A[pa][qa] = 0.0;
-          A[qa][pa] = 0.0;
-        } else {
-          double ca = rc[ia], sa = rs[ia], cb = rc[ib], sb = rs[ib];
-          double w11 = A[pa][pb], w12 = A[pa][qb], w21 = A[qa][pb], w22 = A[qa][qb];
-          double r11 = ca * w11 - sa * w21, r12 = ca * w12 - sa * w22;
-          double r21 = sa * w11 + ca * w21, r22 = sa * w12 + ca * w22;
-          A[pa][pb] = cb * r11 - sb * r12;
-          A[pa][qb] = sb * r11 + cb * r12;
-          A[qa][pb] = cb * r21 - sb * r22;
-          A[qa][qb] = sb * r21 + cb * r22;
+          t = fabs(th) > 1e150 ? 0.5 / th : copysign(1.0, th) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+          c = rsqrt(fma(t, t, 1.0));
+          sn = t * c;
+          act = 1;
         }
       }
-      for (int it = tid; it < np * npairs; it += 256) {
-        int x = it / npairs, ib = it % npairs;
-        int pb = rp[ib], qb = rq[ib];
-        double cb = rc[ib], sb = rs[ib];
-        double v1 = B[x][pb], v2 = B[x][qb];
-        B[x][pb] = cb * v1 - sb * v2;
-        B[x][qb] = sb * v1 + cb * v2;
+      if (__ballot(act) == 0ull) continue;   // same decision in every wave
+      const int nxt = cur ^ 1;
+      for (int j = 0; j < BITER; ++j) {
+        int blk = tid + 256 * j;
+        bool ok = blk < PAIRS * PAIRS;
+        int ia = ok ? blk / PAIRS : 0, ib = ok ? blk % PAIRS : 0;
+        double ca = __shfl(c, ia, 64), sa = __shfl(sn, ia, 64), ta = __shfl(t, ia, 64);
+        double cb = __shfl(c, ib, 64), sb = __shfl(sn, ib, 64);
+        if (ok) {
+          int pa = L.tp[r][ia], qa = L.tq[r][ia], pb = L.tp[r][ib], qb = L.tq[r][ib];
+          if (ia == ib) {
+            double apq = L.A[cur][pa][qa];
+            L.A[nxt][pa][pa] = L.A[cur][pa][pa] - ta * apq;
+            L.A[nxt][qa][qa] = L.A[cur][qa][qa] + ta * apq;
+            L.A[nxt][pa][qa] = 0.0;
+            L.A[nxt][qa][pa] = 0.0;
+          } else {
+            double w11 = L.A[cur][pa][pb], w12 = L.A[cur][pa][qb];
+            double w21 = L.A[cur][qa][pb], w22 = L.A[cur][qa][qb];
+            double r11 = ca * w11 - sa * w21, r12 = ca * w12 - sa * w22;
+            double r21 = sa * w11 + ca * w21, r22 = sa * w12 + ca * w22;
+            L.A[nxt][pa][pb] = cb * r11 - sb * r12;
+            L.A[nxt][pa][qb] = sb * r11 + cb * r12;
+            L.A[nxt][qa][pb] = cb * r21 - sb * r22;
+            L.A[nxt][qa][qb] = sb * r21 + cb * r22;
+          }
+        }
+      }
+      for (int j = 0; j < VITER; ++j) {
+        int it = tid + 256 * j;
+        bool ok = it < NP * PAIRS;
+        int x = ok ? it / PAIRS : 0, ib = ok ? it % PAIRS : 0;
+        double cb = __shfl(c, ib, 64), sb = __shfl(sn, ib, 64);
+        if (ok) {
+          int pb = L.tp[r][ib], qb = L.tq[r][ib];
+          double v1 = L.V[x][pb], v2 = L.V[x][qb];
+          L.V[x][pb] = cb * v1 - sb * v2;
+          L.V[x][qb] = sb * v1 + cb * v2;
+        }
       }
       __syncthreads();
+      cur = nxt;
     }
   }
+  return cur;
+}
+
+// Ranks of the eigenvalues (descending, ties by index) into L.rk; writes
+// lam[rank] and Vout[row * n + rank] (n x n) when given.
+template <int NP>
+__device__ void jacobi_sort_store(JacLds<NP>& L, int cur, int n, double* lam, double* Vout) {
+  const int tid = threadIdx.x;
   if (tid < n) {
-    double lx = A[tid][tid];
+    double lx = L.A[cur][tid][tid];
     int rank = 0;
     for (int y = 0; y < n; ++y) {
-      double ly = A[y][y];
+      double ly = L.A[cur][y][y];
       rank += (ly > lx) || (ly == lx && y < tid);
     }
-    rk[tid] = rank;
-    a.lam[rank] = lx;
+    L.rk[tid] = rank;
+    if (lam) lam[rank] = lx;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += 256) {
-    int row = e / n, x = e % n;
-    a.V[row * n + rk[x]] = B[row][x];
+  if (Vout)
+    for (int e = tid; e < n * NP; e += 256) {
+      int row = e / NP, x = e % NP;
+      if (x < n) Vout[row * n + L.rk[x]] = L.V[row][x];
+    }
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_jacobi_small(JacArgs a) {
+  if (a.s.skip()) return;
+  __shared__ JacLds<NP> L;
+  const int n = (int)a.n, tid = threadIdx.x;
+  const bool warm = (*a.tag == a.tagval);
+  for (int e = tid; e < NP * NP; e += 256) {
+    int x = e / NP, y = e % NP;
+    L.A[0][x][y] = (x < n && y < n) ? a.G[x * n + y] : 0.0;
   }
+  __syncthreads();
+  jacobi_setup<NP>(L, n, warm, a.V);
+  bool conv;
+  int cur = jacobi_core<NP>(L, &conv);
+  jacobi_sort_store<NP>(L, cur, n, a.lam, a.V);
   if (tid == 0) {
     *a.tag = a.tagval;
     if (!conv) atomicCAS(a.s.st, 0, MACH_ENOCONV);
+  }
+}
+
+// One mode update of a HOOI sweep, sides up to 64, in one workgroup:
+// G = sum of the Gram partials (fixed order); warm-started Jacobi; the
+// eigenpairs sorted and kept for the next sweep.  Row-side Gram: the top R
+// eigenvectors are the factor; the sign rule is applied and the float64
+// factor and its float32 copy stored.  Column-side Gram: M = V_R
+// Lambda_R^{-1/2} (s x 16) is written for the back-projection kernels.
+struct SolveArgs {
+  const double* part;
+  uint32_t nchunk, s, I, R;
+  int kside;
+  double* V;
+  double* lam;
+  int32_t* tag;
+  int32_t tagval;
+  double* M;
+  double* Aout;
+  float* af;
+  int32_t* stats;
+  Status st;
+};
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_mode_solve(SolveArgs a) {
+  if (a.st.skip()) return;
+  __shared__ JacLds<NP> L;
+  __shared__ double sgn[16];
+  const int n = (int)a.s, tid = threadIdx.x;
+  const uint32_t n2 = a.s * a.s;
+  for (int e = tid; e < NP * NP; e += 256) {
+    int x = e / NP, y = e % NP;
+    double g = 0.0;
+    if (x < n && y < n)
+      for (uint32_t c = 0; c < a.nchunk; ++c) g += a.part[(size_t)c * n2 + x * n + y];
+    L.A[0][x][y] = g;
+  }
+  __syncthreads();
+  const bool warm = (*a.tag == a.tagval);
+  jacobi_setup<NP>(L, n, warm, a.V);
+  bool conv;
+  int used = 0;
+  int cur = jacobi_core<NP>(L, &conv, &used);
+  jacobi_sort_store<NP>(L, cur, n, a.lam, a.V);
+  if (tid == 0 && a.stats) *a.stats = used + (warm ? 1000 : 0);
+  __syncthreads();
+  // rk maps eigen index -> rank; invert it for the top R columns
+  __shared__ int col_of_rank[16];
+  if (tid < n && L.rk[tid] < (int)a.R) col_of_rank[L.rk[tid]] = tid;
+  __syncthreads();
+  if (tid == 0) {
+    *a.tag = a.tagval;
+    if (!conv) atomicCAS(a.st.st, 0, MACH_ENOCONV);
+  }
+  if (a.kside) {
+    if (tid == 0) {
+      double l0 = L.A[cur][col_of_rank[0]][col_of_rank[0]];
+      double lr = L.A[cur][col_of_rank[a.R - 1]][col_of_rank[a.R - 1]];
+      if (!(lr > 1e-13 * l0)) atomicCAS(a.st.st, 0, MACH_EDEGENERATE);
+    }
+    for (int e = tid; e < n * 16; e += 256) {
+      int x = e >> 4, r = e & 15;
+      double v = 0.0;
+      if (r < (int)a.R) {
+        int col = col_of_rank[r];
+        v = L.V[x][col] / sqrt(fmax(L.A[cur][col][col], 1e-300));
+      }
+      a.M[e] = v;
+    }
+    return;
+  }
+  // row side: factor = top R eigenvectors (I == n rows); sign rule per column
+  if (tid < (int)a.R) {
+    int col = col_of_rank[tid];
+    double best = -1.0, val = 0.0;
+    for (int x = 0; x < n; ++x) {
+      double v = L.V[x][col];
+      if (fabs(v) > best) {
+        best = fabs(v);
+        val = v;
+      }
+    }
+    sgn[tid] = val < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * 16; e += 256) {
+    int x = e >> 4, r = e & 15;
+    double v = r < (int)a.R ? sgn[r] * L.V[x][col_of_rank[r]] : 0.0;
+    if (r < (int)a.R) a.Aout[(size_t)x * a.R + r] = v;
+    a.af[e] = (float)v;
+  }
+}
+
+// Column-side back-projection Aw = Y_(k) M (I x 16, float64) from the
+// float32 view (O, I, Q) of Y_k, plus per-workgroup partials of Aw^T Aw.
+__global__ __launch_bounds__(256) void k_bp_tall(const float* __restrict__ Y, uint32_t O, uint32_t I,
+                                                 uint32_t Q, const double* __restrict__ M, uint32_t R,
+                                                 double* __restrict__ Aw, double* __restrict__ part,
+                                                 Status s) {
+  if (s.skip()) return;
+  __shared__ double Ms[256][17];
+  __shared__ double rows[256][17];
+  const uint32_t K = O * Q;
+  for (uint32_t e = threadIdx.x; e < K * 16; e += 256) Ms[e >> 4][e & 15] = M[e];
+  __syncthreads();
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  double acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  if (i < I) {
+    for (uint32_t o = 0; o < O; ++o) {
+      const float* yrow = Y + ((size_t)o * I + i) * Q;
+      for (uint32_t q = 0; q < Q; ++q) {
+        double y = (double)yrow[q];
+        const uint32_t kappa = o * Q + q;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = fma(y, Ms[kappa][r], acc[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Aw[(size_t)i * 16 + r] = (uint32_t)r < R ? acc[r] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) rows[threadIdx.x][r] = (i < I && (uint32_t)r < R) ? acc[r] : 0.0;
+  __syncthreads();
+  const int x = threadIdx.x >> 4, y = threadIdx.x & 15;
+  double g = 0.0;
+  for (int t = 0; t < 256; ++t) g = fma(rows[t][x], rows[t][y], g);
+  part[(size_t)blockIdx.x * 256 + threadIdx.x] = g;
+}
+
+// One Cholesky-QR pass on Aw (I x 16): every workgroup sums the Gram
+// partials (fixed order), factors S = L L^T in one wave, and replaces its
+// rows by a L^{-T}; then writes per-workgroup column maxima of |a| for the
+// sign rule.
+__global__ __launch_bounds__(256) void k_chol_apply_tall(double* __restrict__ Aw, uint32_t I, uint32_t R,
+                                                         const double* __restrict__ part, uint32_t nchunk,
+                                                         double* __restrict__ pv, uint32_t* __restrict__ pi,
+                                                         Status s) {
+  if (s.skip()) return;
+  __shared__ double S[16][17];
+  __shared__ double Li[16][17];
+  __shared__ double bv[256];
+  __shared__ uint32_t bi[256];
+  const int tid = threadIdx.x;
+  {
+    double g = 0.0;
+    for (uint32_t c = 0; c < nchunk; ++c) g += part[(size_t)c * 256 + tid];
+    S[tid >> 4][tid & 15] = g;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // lane x owns row x of S; right-looking Cholesky, then L^{-1} by
+    // forward substitution (column j of L^{-1} in lane j).
+    const int x = tid;
+    for (uint32_t j = 0; j < R; ++j) {
+      if (x == (int)j) S[j][j] = sqrt(fmax(S[j][j], 1e-300));
+      __builtin_amdgcn_wave_barrier();
+      double d = S[j][j];
+      if (x > (int)j && x < (int)R) S[x][j] /= d;
+      __builtin_amdgcn_wave_barrier();
+      if (x > (int)j && x < (int)R)
+        for (uint32_t k = j + 1; k <= (uint32_t)x; ++k) S[x][k] -= S[x][j] * S[k][j];
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (x < 16)
+      for (int i = 0; i < 16; ++i) Li[i][x] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    if (x < (int)R) {
+      for (uint32_t i = x; i < R; ++i) {
+        double v = (i == (uint32_t)x) ? 1.0 : 0.0;
+        for (uint32_t k = x; k < i; ++k) v -= S[i][k] * Li[k][x];
+        Li[i][x] = v / S[i][i];
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t i = blockIdx.x * 256 + tid;
+  double out[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) out[r] = 0.0;
+  if (i < I) {
+    double a[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = Aw[(size_t)i * 16 + r];
+    // a L^{-T}: out_j = sum_{k <= j} a_k Linv[j][k]
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k <= j; ++k) v = fma(a[k], Li[j][k], v);
+      out[j] = (uint32_t)j < R ? v : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Aw[(size_t)i * 16 + r] = out[r];
+  }
+  // column maxima over this workgroup's rows (value, then lowest row)
+  for (int r = 0; r < 16; ++r) {
+    bv[tid] = i < I ? fabs(out[r]) : -1.0;
+    bi[tid] = i;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) {
+        double v2 = bv[tid + o];
+        uint32_t i2 = bi[tid + o];
+        if (v2 > bv[tid] || (v2 == bv[tid] && i2 < bi[tid])) {
+          bv[tid] = v2;
+          bi[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      pv[blockIdx.x * 16 + r] = bv[0];
+      pi[blockIdx.x * 16 + r] = bi[0];
+    }
+    __syncthreads();
   }
 }
 
@@ -387,7 +693,7 @@ __global__ void k_copy64(const double* __restrict__ src, double* __restrict__ ds
 __global__ __launch_bounds__(256) void k_ss_check(const double* __restrict__ Z2, const double* __restrict__ Qr,
                                                   uint32_t ld, uint32_t M, const double* __restrict__ theta,
                                                   uint32_t R, double tol, int32_t* done, int last,
-                                                  Status s) {
+                                                  int32_t* stat_it, int32_t it, Status s) {
   if (s.skip()) return;
   __shared__ double res[16][4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -412,8 +718,13 @@ __global__ __launch_bounds__(256) void k_ss_check(const double* __restrict__ Z2,
       worst = v > worst ? v : worst;
     }
     double ref = fabs(theta[0]);
-    if (worst <= tol * ref) *done = 1;
-    else if (last && worst > 1e-8 * ref) atomicCAS(s.st, 0, MACH_ENOCONV);
+    if (worst <= tol * ref) {
+      *done = 1;
+      *stat_it = it + 1;
+    } else if (last) {
+      *stat_it = 10000 + it + 1;
+      if (worst > 1e-8 * ref) atomicCAS(s.st, 0, MACH_ENOCONV);
+    }
   }
 }
 
@@ -484,6 +795,42 @@ __global__ __launch_bounds__(256) void k_backproject_xhat(const uint64_t* __rest
   }
   for (uint32_t r = 0; r < 16; ++r)
     Aw[(size_t)i * 16 + r] = r < R ? acc[r] / sqrt(fmax(lam[r], 1e-300)) : 0.0;
+}
+
+// Column-side Gram of Xhat_(n) when mode n is the only tail mode: row i of
+// the matricization is tail column c = i of the column-grouped copy and
+// the matricization column of an entry is its head row l / MT.  One wave
+// per row: lanes take entries, then a fixed butterfly sums the lanes.
+__global__ __launch_bounds__(256) void k_backproject_cols(const Entry* __restrict__ coo_t,
+                                                          const uint32_t* __restrict__ colptr,
+                                                          uint32_t I, FastDiv fMT,
+                                                          const double* __restrict__ V, uint32_t ldv,
+                                                          const double* __restrict__ lam, uint32_t R,
+                                                          double* __restrict__ Aw, Status s) {
+  if (s.skip()) return;
+  const int lane = threadIdx.x & 63;
+  const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!(lam[R - 1] > 1e-13 * lam[0])) atomicCAS(s.st, 0, MACH_EDEGENERATE);
+  }
+  double acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  if (i < I) {
+    for (uint32_t e = colptr[i] + lane; e < colptr[i + 1]; e += 64) {
+      Entry en = coo_t[e];
+      const double* v = V + (size_t)fMT.div(en.l) * ldv;
+      double x = (double)en.v;
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if ((uint32_t)r < R) acc[r] = fma(x, v[r], acc[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    for (int m = 32; m > 0; m >>= 1) acc[r] += __shfl_xor(acc[r], m, 64);
+  if (i < I && lane < 16)
+    Aw[(size_t)i * 16 + lane] = (uint32_t)lane < R ? acc[lane] / sqrt(fmax(lam[lane], 1e-300)) : 0.0;
 }
 
 // Per-chunk column maxima of |Aw| (value, then lowest row).
@@ -571,19 +918,22 @@ __global__ void k_fit(const double* __restrict__ lam, uint32_t R, const SampleHd
   if (core2_out) *core2_out = g2;
 }
 
-// G[(q*O + o)*R + r] = (1/p) sum_i A[i][r] Y[(o*I + i)*Q + q]
-__global__ void k_core(const float* __restrict__ Y, uint32_t O, uint32_t I, uint32_t Q,
-                       const double* __restrict__ A, uint32_t R, double* __restrict__ G,
-                       const SampleHdr* hdr, const int32_t* st) {
+// G[(q*O + o)*R + r] = (1/p) sum_i A[i][r] Y[(o*I + i)*Q + q]; one
+// workgroup per core entry, fixed-order tree over i.
+__global__ __launch_bounds__(256) void k_core(const float* __restrict__ Y, uint32_t O, uint32_t I,
+                                              uint32_t Q, const double* __restrict__ A, uint32_t R,
+                                              double* __restrict__ G, const SampleHdr* hdr,
+                                              const int32_t* st) {
   if (hdr->status != 0 || *st != 0) return;
-  uint32_t e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= O * Q * R) return;
+  __shared__ double red[2][4];
+  uint32_t e = blockIdx.x;
   uint32_t r = e % R, t = e / R;
   uint32_t o = t % O, q = t / O;
-  double acc = 0.0;
-  for (uint32_t i = 0; i < I; ++i)
+  double acc = 0.0, dummy = 0.0;
+  for (uint32_t i = threadIdx.x; i < I; i += 256)
     acc = fma(A[(size_t)i * R + r], (double)Y[((size_t)o * I + i) * Q + q], acc);
-  G[e] = acc / hdr->p;
+  block_sum2(acc, dummy, red);
+  if (threadIdx.x == 0) G[e] = acc / hdr->p;
 }
 
 __global__ __launch_bounds__(256) void k_norm2(const double* __restrict__ G, uint32_t n, double* out,
@@ -665,7 +1015,12 @@ void jacobi(const Ctx& c, const double* G, uint32_t n, double* V, double* lam, i
   a.tag = tag;
   a.tagval = tagval;
   a.s = c.stat(with_done);
-  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(256), 0, c.st, a);
+  if (n <= 16)
+    hipLaunchKernelGGL(k_jacobi_small<16>, dim3(1), dim3(256), 0, c.st, a);
+  else if (n <= 32)
+    hipLaunchKernelGGL(k_jacobi_small<32>, dim3(1), dim3(256), 0, c.st, a);
+  else
+    hipLaunchKernelGGL(k_jacobi_small<64>, dim3(1), dim3(256), 0, c.st, a);
 }
 
 // Top eigenpairs of the s x s matrix G (s > 64) by block subspace iteration
@@ -673,7 +1028,7 @@ void jacobi(const Ctx& c, const double* G, uint32_t n, double* V, double* lam, i
 // start if *tag == tagval); on return its first columns are the Ritz
 // vectors, lam (64) the Ritz values, descending.
 void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double* Q, double* lam,
-                   int32_t* tag, int32_t tagval, int maxit) {
+                   int32_t* tag, int32_t tagval, int maxit, int32_t* stat_it) {
   const uint32_t b = s < kBlock ? s : kBlock;
   int32_t* tags = c.tags();
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagDone, 0);
@@ -710,7 +1065,7 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
                          s * kBlock, sd);
       hipLaunchKernelGGL(k_copy64, dim3(1), dim3(256), 0, c.st, lamH, lam, b, sd);
       hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, Z2, Qr, kBlock, s, lamH, R, 1e-12,
-                         tags + kTagDone, last ? 1 : 0, c.stat(true));
+                         tags + kTagDone, last ? 1 : 0, stat_it, it, c.stat(true));
     }
   }
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tag, tagval);
@@ -742,10 +1097,49 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
   (void)si;
   Ctx c{&SL, ws, hdr, st};
   const ModePlan& m = SL.mp[k];
+  int32_t tagval = 0x4d000000 | (k << 16) | (int32_t)m.s;
+  if (m.s <= (uint32_t)kSmallEig) {
+    uint32_t nchunk = 1;
+    hipError_t e = launch_gram_y_partials(SL, ws, k, hdr, st, &nchunk);
+    if (e != hipSuccess) return e;
+    SolveArgs a;
+    a.part = c.d(SL.Gpart);
+    a.nchunk = nchunk;
+    a.s = m.s;
+    a.I = m.I;
+    a.R = m.R;
+    a.kside = m.kside;
+    a.V = c.d(m.V);
+    a.lam = c.d(m.lam);
+    a.tag = c.tags() + k;
+    a.tagval = tagval;
+    a.M = c.d(SL.small);
+    a.Aout = A_out;
+    a.af = (float*)(ws + SL.af[k]);
+    a.stats = (int32_t*)(ws + SL.status + 96) + k;
+    a.st = c.stat();
+    if (m.s <= 16)
+      hipLaunchKernelGGL(k_mode_solve<16>, dim3(1), dim3(256), 0, st, a);
+    else if (m.s <= 32)
+      hipLaunchKernelGGL(k_mode_solve<32>, dim3(1), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_mode_solve<64>, dim3(1), dim3(256), 0, st, a);
+    if (m.kside) {
+      uint32_t nwg = cdiv(m.I, 256);
+      double* part = c.d(SL.part);
+      hipLaunchKernelGGL(k_bp_tall, dim3(nwg), dim3(256), 0, st, (const float*)(ws + m.ybuf), m.O, m.I,
+                         m.Q, c.d(SL.small), m.R, c.d(SL.Aw), part, c.stat());
+      hipLaunchKernelGGL(k_chol_apply_tall, dim3(nwg), dim3(256), 0, st, c.d(SL.Aw), m.I, m.R, part, nwg,
+                         c.d(SL.pv), (uint32_t*)(ws + SL.pi), c.stat());
+      hipLaunchKernelGGL(k_sign_store, dim3(cdiv((uint64_t)m.I * 16, 256)), dim3(256), 0, st,
+                         c.d(SL.Aw), m.I, m.R, c.d(SL.pv), (const uint32_t*)(ws + SL.pi), nwg, A_out,
+                         (float*)(ws + SL.af[k]), c.stat());
+    }
+    return hipGetLastError();
+  }
   hipError_t e = launch_gram_y(SL, ws, k, hdr, st);
   if (e != hipSuccess) return e;
   const double* G = c.d(SL.G);
-  int32_t tagval = 0x4d000000 | (k << 16) | (int32_t)m.s;
   double* V;
   uint32_t ldv;
   if (m.s <= (uint32_t)kSmallEig) {
@@ -755,7 +1149,8 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
   } else {
     V = c.d(m.Q64);
     ldv = kBlock;
-    subspace_topk(c, G, m.s, m.R, V, c.d(m.lam), c.tags() + k, tagval, 24);
+    subspace_topk(c, G, m.s, m.R, V, c.d(m.lam), c.tags() + k, tagval, 24,
+                  (int32_t*)(ws + SL.status + 96) + k);
   }
   if (m.kside) {
     uint32_t J = m.O * m.Q;
@@ -788,10 +1183,15 @@ hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const So
     jacobi(c, G, s, V, lam, tagc, 0x48000000 | (int32_t)s, false);
   } else {
     ldv = kBlock;
-    subspace_topk(c, G, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 80);
+    subspace_topk(c, G, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 80,
+                  (int32_t*)(ws + SL.status + 128) + n);
   }
   const uint32_t I = si.dims[n];
-  if (SL.hosvd_kside[n]) {
+  if (SL.hosvd_kside[n] && n == si.d - 1 && si.h == si.d - 1) {
+    hipLaunchKernelGGL(k_backproject_cols, dim3(cdiv(I, 4)), dim3(256), 0, st, sp.coo_t, sp.colptr, I,
+                       si.fMT, V, ldv, lam, (uint32_t)R, c.d(SL.Aw), c.stat());
+    cholqr2(c, c.d(SL.Aw), 16, I, (uint32_t)R, false);
+  } else if (SL.hosvd_kside[n]) {
     uint32_t J = si.N / I;
     hipLaunchKernelGGL(k_backproject_xhat, dim3(cdiv(I, 256)), dim3(256), 0, st, sp.bitmap, sp.wrank,
                        sp.coo_l, I, si.stride[n], J, si.fstride[n], V, ldv, lam, (uint32_t)R,
@@ -809,7 +1209,7 @@ hipError_t launch_fit(const SolverLayout& SL, char* ws, int k, const SampleHdr* 
                       hipStream_t st) {
   const ModePlan& m = SL.mp[k];
   hipLaunchKernelGGL(k_fit, dim3(1), dim3(64), 0, st, (const double*)(ws + m.lam), m.R, hdr,
-                     (const int32_t*)(ws + SL.status), fit, (double*)(ws + SL.status + 128));
+                     (const int32_t*)(ws + SL.status), fit, (double*)(ws + SL.status + 192));
   return hipGetLastError();
 }
 
@@ -818,7 +1218,7 @@ hipError_t launch_core(const ShapeInfo& si, const SolverLayout& SL, char* ws, co
   const ModePlan& m = SL.mp[si.d - 1];
   uint32_t n = m.O * m.Q * m.R;
   const int32_t* stp = (const int32_t*)(ws + SL.status);
-  hipLaunchKernelGGL(k_core, dim3(cdiv(n, 256)), dim3(256), 0, st, (const float*)(ws + m.ybuf), m.O,
+  hipLaunchKernelGGL(k_core, dim3(n), dim3(256), 0, st, (const float*)(ws + m.ybuf), m.O,
                      m.I, m.Q, A_last, m.R, G, hdr, stp);
   if (norm2)
     hipLaunchKernelGGL(k_norm2, dim3(1), dim3(256), 0, st, G, n, norm2, hdr, stp);

@@ -134,6 +134,20 @@ __global__ void k_gram_reduce(const double* __restrict__ part, uint32_t nchunk, 
   G[e] = s;
 }
 
+// Picks the summation slicing; returns the number of slices.
+inline uint32_t gram_slices(GramArgs& a, size_t part_elems) {
+  uint32_t tiles = (a.X + 63) / 64;
+  uint64_t n2 = (uint64_t)a.X * a.X;
+  uint32_t nchunk = 1;
+  while (nchunk < 1024 && (uint64_t)tiles * tiles * nchunk < 512 &&
+         a.Z / (2 * nchunk) >= 128 && n2 * (2 * nchunk) <= part_elems)
+    nchunk *= 2;
+  a.zchunk = (a.Z + nchunk - 1) / nchunk;
+  a.zchunk = (a.zchunk + 31) / 32 * 32;
+  nchunk = (a.Z + a.zchunk - 1) / a.zchunk;
+  return nchunk < 1 ? 1 : nchunk;
+}
+
 template <typename Load>
 hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream_t st) {
   uint32_t tiles = (a.X + 63) / 64;
@@ -157,6 +171,28 @@ hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream
 }
 
 }  // namespace
+
+// Gram partials of Y_k (dense float32 view): SL.Gpart[c][X][X], c < *nchunk.
+hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
+                                  hipStream_t st, uint32_t* nchunk) {
+  const ModePlan& m = SL.mp[k];
+  GramArgs a{};
+  a.I = m.I;
+  a.Q = m.Q;
+  a.J = m.O * m.Q;
+  a.fQ = make_fastdiv(m.Q);
+  a.kside = m.kside;
+  a.X = m.s;
+  a.Z = m.kside ? m.I : a.J;
+  a.part = (double*)(ws + SL.Gpart);
+  a.st_solver = (const int32_t*)(ws + SL.status);
+  a.hdr = hdr;
+  *nchunk = gram_slices(a, SL.Gpart_elems);
+  uint32_t tiles = (a.X + 63) / 64;
+  DenseLoad ld{(const float*)(ws + m.ybuf)};
+  hipLaunchKernelGGL((k_gram<DenseLoad>), dim3(tiles, tiles, *nchunk), dim3(256), 0, st, a, ld);
+  return hipGetLastError();
+}
 
 // Gram of Y_k (dense float32 view) into SL.G.
 hipError_t launch_gram_y(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,

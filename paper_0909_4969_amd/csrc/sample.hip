@@ -148,6 +148,54 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, uin
   if (t == 1023) a[n] = part[1023];
 }
 
+// Multi-block exclusive scan in place over a[0..n) with a[n] = total:
+// per-block sums, one-workgroup scan of those, then per-block rescan.
+constexpr uint32_t kScanBlock = 4096;
+
+__global__ __launch_bounds__(256) void k_scan_blocksum(const uint32_t* __restrict__ a, uint32_t n,
+                                                       uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t sh[4];
+  uint32_t b0 = blockIdx.x * kScanBlock, s = 0;
+  for (uint32_t i = b0 + threadIdx.x; i < min(n, b0 + kScanBlock); i += 256) s += a[i];
+  s = block_sum256<uint32_t>(s, sh);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(uint32_t* __restrict__ a, uint32_t n,
+                                                    const uint32_t* __restrict__ boff) {
+  __shared__ uint32_t sh[4];
+  const uint32_t b0 = blockIdx.x * kScanBlock;
+  uint32_t run = boff[blockIdx.x];
+  // 16 elements per thread, contiguous per thread
+  const uint32_t base = b0 + threadIdx.x * 16;
+  uint32_t v[16], s = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[k] = (base + k < n) ? a[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t ex = block_exscan256(s, sh, &tot);
+  run += ex;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (base + k < n) a[base + k] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) a[n] = boff[gridDim.x];
+}
+
+void scan_u32(uint32_t* a, uint32_t n, uint32_t* bsum, hipStream_t st) {
+  uint32_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb <= 1) {
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, a, n);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_blocksum, dim3(nb), dim3(256), 0, st, a, n, bsum);
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, bsum, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, st, a, n, bsum);
+}
+
 // Four consecutive inputs at a 4-element-aligned index (the tensor base is
 // at least 16-byte aligned): one 16-byte load for float, two for double.
 __device__ __forceinline__ void load4(const float* p, float x[4]) {
@@ -329,7 +377,7 @@ hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, doubl
   hipLaunchKernelGGL(k_sample_mask, dim3(si.nblk), dim3(kThreads), 0, st, si.N, thresh,
                      (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)window,
                      (uint32_t)(window >> 32), bitmap, blkcnt);
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, blkcnt, si.nblk);
+  scan_u32(blkcnt, si.nblk, (uint32_t*)(ws + L.scan_tmp), st);
   if (x_is_f64)
     hipLaunchKernelGGL(k_sample_compact<double>, dim3(si.nblk), dim3(kThreads), 0, st,
                        (const double*)X, si.N, bitmap, blkcnt, wrank, coo_l, cap, sumsq_part);
@@ -343,7 +391,7 @@ hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, doubl
   hipLaunchKernelGGL(k_headrow, dim3((si.MH + 255) / 256), dim3(256), 0, st, si, headrow);
   dim3 g((si.MT + 63) / 64, (si.nrb + 3) / 4);
   hipLaunchKernelGGL(k_csc_count, g, dim3(256), 0, st, si, bitmap, headrow, csc_cnt);
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, csc_cnt, si.MT * si.nrb);
+  scan_u32(csc_cnt, si.MT * si.nrb, (uint32_t*)(ws + L.scan_tmp), st);
   hipLaunchKernelGGL(k_csc_fill, g, dim3(256), 0, st, si, bitmap, wrank, headrow, csc_cnt, coo_l,
                      coo_t, colptr, hdr);
   return hipGetLastError();

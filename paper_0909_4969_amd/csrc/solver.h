@@ -39,8 +39,10 @@ struct ModePlan {
 constexpr uint32_t kBlock = 64;          // subspace block for sides > kSmallEig
 
 // Status region: int32 status word at +0, int32 tags[16] at +16 (eigen
-// warm-start tags of modes 0..7, then kTagRR, kTagCold, kTagDone), doubles
-// from +128.
+// warm-start tags of modes 0..7, then kTagRR, kTagCold, kTagDone), int32
+// solver statistics at +96 (Jacobi sweeps of the last solve of modes 0..7,
+// +1000 if warm-started; subspace-iteration steps of the HOSVD of modes
+// 0..7 at +128, +10000 if not converged), doubles from +192.
 constexpr int kTagRR = 8, kTagCold = 9, kTagDone = 10;
 
 struct SolverLayout {
@@ -98,5 +100,10 @@ hipError_t launch_core(const ShapeInfo& si, const SolverLayout& SL, char* ws, co
 hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
                              char* ws, int n, int R, double* A_out, hipStream_t st);
 hipError_t launch_solver_init(const SolverLayout& SL, char* ws, hipStream_t st);
+
+// Kernel timing hook (api.hip): while enabled, the sparse passes are
+// launched with start/stop events taken from a pool; which = 0 for the
+// pass over head rows, 1 for the pass over tail columns.
+bool timing_events(int which, hipEvent_t* e0, hipEvent_t* e1);
 
 }  // namespace mach

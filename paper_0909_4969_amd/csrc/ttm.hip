@@ -12,6 +12,8 @@
 // sub-ranges, one per lane, so every lane walks whole fibers in registers;
 // the G partial results are then summed by a fixed xor butterfly.  The
 // result depends only on the data, never on scheduling.
+#include <hip/hip_ext.h>
+
 #include "solver.h"
 
 namespace mach {
@@ -59,38 +61,64 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
   for (int j = 0; j < NS; ++j) s[j] = 0.f;
   uint32_t cur = 0xffffffffu;
   const uint32_t segbase = seg * a.MT;
-  for (uint32_t e = lo; e < hi; ++e) {
-    Entry en = a.ent[e];
-    uint32_t x = a.csc ? a.fMT.div(en.l) : en.l - segbase;
-    uint32_t iin = x, iout = 0;
-    if (NQ == 2) {
-      uint32_t h = a.flo.div(x);
-      uint32_t l = x - h * a.flo.d;
-      iin = a.inner_is_lo ? l : h;
-      iout = a.inner_is_lo ? h : l;
-      if (iout != cur) {
+  // Batches of U entries: all loads of a batch are issued before any use,
+  // so each lane waits for memory once per batch rather than per entry.
+  constexpr int U = (NS + 4 * RI <= 160) ? 4 : 2;
+  for (uint32_t e0 = lo; e0 < hi; e0 += U) {
+    Entry en[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e0 + u < hi) {
+        en[u] = a.ent[e0 + u];
+      } else {
+        en[u].l = a.csc ? 0u : segbase;
+        en[u].v = 0.f;
+      }
+    }
+    uint32_t iin[U], iout[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t x = a.csc ? a.fMT.div(en[u].l) : en[u].l - segbase;
+      iin[u] = x;
+      iout[u] = 0;
+      if (NQ == 2) {
+        uint32_t h = a.flo.div(x);
+        uint32_t l = x - h * a.flo.d;
+        iin[u] = a.inner_is_lo ? l : h;
+        iout[u] = a.inner_is_lo ? h : l;
+      }
+    }
+    float4 w[U][RI / 4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float4* ap = reinterpret_cast<const float4*>(a.Ain + (size_t)iin[u] * 16);
+#pragma unroll
+      for (int q = 0; q < RI / 4; ++q) w[u][q] = ap[q];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (NQ == 2 && e0 + u < hi && iout[u] != cur) {
         if (cur != 0xffffffffu) {
           const float* ao = a.Aout + (size_t)cur * 16;
 #pragma unroll
           for (int o = 0; o < RO; ++o) {
-            float w = ao[o];
+            float wo = ao[o];
 #pragma unroll
-            for (int j = 0; j < RI; ++j) s[o * RI + j] = fmaf(w, t[j], s[o * RI + j]);
+            for (int j = 0; j < RI; ++j) s[o * RI + j] = fmaf(wo, t[j], s[o * RI + j]);
           }
 #pragma unroll
           for (int j = 0; j < RI; ++j) t[j] = 0.f;
         }
-        cur = iout;
+        cur = iout[u];
       }
-    }
-    const float4* ap = reinterpret_cast<const float4*>(a.Ain + (size_t)iin * 16);
+      const float v = en[u].v;
 #pragma unroll
-    for (int q = 0; q < RI / 4; ++q) {
-      float4 w = ap[q];
-      t[4 * q + 0] = fmaf(en.v, w.x, t[4 * q + 0]);
-      t[4 * q + 1] = fmaf(en.v, w.y, t[4 * q + 1]);
-      t[4 * q + 2] = fmaf(en.v, w.z, t[4 * q + 2]);
-      t[4 * q + 3] = fmaf(en.v, w.w, t[4 * q + 3]);
+      for (int q = 0; q < RI / 4; ++q) {
+        t[4 * q + 0] = fmaf(v, w[u][q].x, t[4 * q + 0]);
+        t[4 * q + 1] = fmaf(v, w[u][q].y, t[4 * q + 1]);
+        t[4 * q + 2] = fmaf(v, w[u][q].z, t[4 * q + 2]);
+        t[4 * q + 3] = fmaf(v, w[u][q].w, t[4 * q + 3]);
+      }
     }
   }
   if (NQ == 2) {
@@ -129,7 +157,12 @@ inline int pad4(uint32_t r) { return r <= 4 ? 4 : r <= 8 ? 8 : r <= 12 ? 12 : 16
 template <int NQ, int RI, int RO>
 hipError_t go(const SpcArgs& a, hipStream_t st) {
   uint32_t per = 256u / a.G;
-  hipLaunchKernelGGL((k_spc<NQ, RI, RO>), dim3((a.nseg + per - 1) / per), dim3(256), 0, st, a);
+  dim3 grid((a.nseg + per - 1) / per);
+  hipEvent_t e0, e1;
+  if (timing_events(a.csc, &e0, &e1))
+    hipExtLaunchKernelGGL((k_spc<NQ, RI, RO>), grid, dim3(256), 0, st, e0, e1, 0, a);
+  else
+    hipLaunchKernelGGL((k_spc<NQ, RI, RO>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -164,23 +197,35 @@ int lanes_per_segment(double density, uint32_t dense_len) {
   return G;
 }
 
-// out[(o*R + r)*Q + q] = sum_i A[i*16 + r] * in[(o*I + i)*Q + q]
+// out[(o*R + r)*Q + q] = sum_i A[i*16 + r] * in[(o*I + i)*Q + q].  A
+// workgroup owns 64 consecutive outputs; its 4 waves take every 4th i with
+// two accumulators each, and the partial sums are added in a fixed order.
 __global__ __launch_bounds__(256) void k_dense_ttm(const float* __restrict__ in, uint32_t O, uint32_t I,
                                                    uint32_t Q, const float* __restrict__ A, uint32_t R,
                                                    float* __restrict__ out, const SampleHdr* hdr,
                                                    const int32_t* st_solver) {
   if (hdr->status != 0 || *st_solver != 0) return;
-  uint64_t idx = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  uint64_t total = (uint64_t)O * R * Q;
-  if (idx >= total) return;
-  uint32_t q = (uint32_t)(idx % Q);
-  uint64_t t = idx / Q;
-  uint32_t r = (uint32_t)(t % R);
-  uint32_t o = (uint32_t)(t / R);
-  const float* src = in + (size_t)o * I * Q + q;
-  float acc = 0.f;
-  for (uint32_t i = 0; i < I; ++i) acc = fmaf(A[(size_t)i * 16 + r], src[(size_t)i * Q], acc);
-  out[idx] = acc;
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t idx = (uint64_t)blockIdx.x * 64 + lane;
+  const uint64_t total = (uint64_t)O * R * Q;
+  float acc0 = 0.f, acc1 = 0.f;
+  if (idx < total) {
+    uint32_t q = (uint32_t)(idx % Q);
+    uint64_t t = idx / Q;
+    uint32_t r = (uint32_t)(t % R);
+    uint32_t o = (uint32_t)(t / R);
+    const float* src = in + (size_t)o * I * Q + q;
+    uint32_t i = w;
+    for (; i + 4 < I; i += 8) {
+      acc0 = fmaf(A[(size_t)i * 16 + r], src[(size_t)i * Q], acc0);
+      acc1 = fmaf(A[(size_t)(i + 4) * 16 + r], src[(size_t)(i + 4) * Q], acc1);
+    }
+    if (i < I) acc0 = fmaf(A[(size_t)i * 16 + r], src[(size_t)i * Q], acc0);
+  }
+  red[w][lane] = acc0 + acc1;
+  __syncthreads();
+  if (w == 0 && idx < total) out[idx] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 struct F32Args {
@@ -272,7 +317,7 @@ hipError_t launch_form_y(const ShapeInfo& si, const SolverLayout& SL, char* ws, 
   const float* src = (const float*)(ws + (k < si.h ? SL.TH : SL.TT));
   uint32_t R = SL.mp[m.contract_mode].R;
   uint64_t total = (uint64_t)m.cO * R * m.cQ;
-  hipLaunchKernelGGL(k_dense_ttm, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, src, m.cO,
+  hipLaunchKernelGGL(k_dense_ttm, dim3((uint32_t)((total + 63) / 64)), dim3(256), 0, st, src, m.cO,
                      m.cI, m.cQ, (const float*)(ws + SL.af[m.contract_mode]), R,
                      (float*)(ws + m.ybuf), hdr, (const int32_t*)(ws + SL.status));
   return hipGetLastError();

@@ -26,6 +26,7 @@ EXPORTED = (
     "mach_solver_workspace_bytes", "mach_hosvd", "mach_hooi_sweep", "mach_core",
     "mach_solver_reset", "mach_layout_info", "mach_sample_offsets",
     "mach_read_status", "mach_status_string", "mach_host_selftest",
+    "mach_timing_enable", "mach_timing_read",
 )
 
 
@@ -69,6 +70,8 @@ def _load():
         "mach_read_status": (I32, [P, P, P, IP, ctypes.POINTER(U64), ctypes.POINTER(D)]),
         "mach_status_string": (ctypes.c_char_p, [I32]),
         "mach_host_selftest": (I32, []),
+        "mach_timing_enable": (I32, [I32]),
+        "mach_timing_read": (I32, [I32, ctypes.POINTER(D), IP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -126,6 +129,18 @@ def layout_info(shape):
 
 def host_selftest() -> int:
     return int(LIB.mach_host_selftest())
+
+
+def timing_enable(on: bool):
+    _check("mach_timing_enable", LIB.mach_timing_enable(1 if on else 0))
+
+
+def timing_read(which: int):
+    """(total milliseconds, launches) of the sparse passes of one kind since
+    timing was enabled: which = 0 head-row pass, 1 tail-column pass."""
+    ms, n = ctypes.c_double(), ctypes.c_int32()
+    _check("mach_timing_read", LIB.mach_timing_read(int(which), ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
 
 
 @dataclass
@@ -219,6 +234,15 @@ def hosvd(sw: SampleWorkspace, ranks, solver: torch.Tensor, factors=None, stream
                                         _ptr_array(factors), ctypes.c_void_p(solver.data_ptr()),
                                         solver.numel(), _stream(stream)))
     return factors
+
+
+def solver_stats(solver: torch.Tensor):
+    """Diagnostics kept in the solver workspace (synchronises): per mode,
+    the Jacobi sweeps of its last eigensolve (+1000 when warm-started) and
+    the subspace-iteration steps of its HOSVD eigensolve (+10000 when the
+    residual tolerance was not reached)."""
+    raw = solver[96:160].view(torch.int32).cpu().tolist()
+    return {"jacobi_sweeps": raw[:8], "hosvd_subspace_steps": raw[8:16]}
 
 
 def solver_reset(shape, ranks, solver: torch.Tensor, stream=None):

@@ -59,6 +59,7 @@ def test_hosvd_matches_oracle(name):
         Un = O.unfold(Xh, n)
         tol = subspace_tol(O.eigengap(Un, ranks[n]), O.davis_kahan_bound(Un, ranks[n], 2.0**-24))
         np.testing.assert_allclose(A_g.T @ A_g, np.eye(ranks[n]), atol=1e-12)
+        say(f"  hosvd mode {n}: sin_theta {O.sin_theta(A_o, A_g):.3e} tol {tol:.1e}")
         assert O.sin_theta(A_o, A_g) <= tol, (n, O.sin_theta(A_o, A_g), tol)
 
 
@@ -82,6 +83,7 @@ def test_sweeps_one_step_and_end_to_end(name):
             A_g = dec.factors[n].cpu().numpy()
             np.testing.assert_allclose(A_g.T @ A_g, np.eye(ranks[n]), atol=1e-12)
             s = O.sin_theta(A_one[n], A_g)
+            say(f"  sweep {it} mode {n}: sin_theta {s:.3e} gap {gaps[n]:.2e} tol {subspace_tol(gaps[n], dk[n]):.1e}")
             assert s <= subspace_tol(gaps[n], dk[n]), (it, n, s, gaps[n])
         A_ref, tr = O.hooi_sweep(Xh, A_ref, ranks)
         fit_o = O.fit_from_norms(n2, tr[-1])
@@ -97,6 +99,7 @@ def test_sweeps_one_step_and_end_to_end(name):
     G_o = O.core(Xh, A_ref)
     e_o = O.rel_error(X, G_o, A_ref)
     e_g = O.rel_error(X, O.core(Xh, A_g), A_g)
+    say(f"  rel error gpu {e_g:.8f} oracle {e_o:.8f}; fit {float(dec.fit.cpu()):.8f} {fit_o:.8f}")
     assert abs(e_g - e_o) <= 1e-4 * e_o + 1e-6, (e_g, e_o)
 
 
