@@ -30,6 +30,9 @@ hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, const
                                   hipStream_t st, uint32_t* nchunk);
 hipError_t launch_gram_xhat(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
                             char* ws, int n, hipStream_t st);
+bool sparse_tail_gram_ok(const ShapeInfo& si, const SolverLayout& SL, int n);
+hipError_t launch_gram_tail_sparse(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
+                                   char* ws, hipStream_t st);
 
 namespace {
 
@@ -85,29 +88,56 @@ struct JacArgs {
   double* lam;         // out: eigenvalues, descending
   int32_t* tag;
   int32_t tagval;
+  int rtop;            // leading eigenpairs that must converge
+  double tol2;         // stopping threshold on off-diagonal / diagonal mass
   Status s;
 };
 
 // LDS state of the Jacobi kernels for a padded size NP (power of two).
 template <int NP>
 struct JacLds {
-  double A[2][NP][NP + 1];              // double-buffered matrix
+  double A[NP][NP + 1];                 // the matrix being diagonalised
   double V[NP][NP + 1];                 // accumulated rotations
+  double W[NP][NP + 1];                 // scratch (warm-start products)
+  double rc[NP / 2], rs[NP / 2], rt[NP / 2];
   unsigned char tp[NP - 1][NP / 2], tq[NP - 1][NP / 2];
   int rk[NP];
-  double red[2][4];
+  double red[2][16];
 };
 
+// Block-wide sums of two values over NT threads (fixed order).
+template <int NT>
+__device__ void block_sum2n(double& a, double& b, double (*red)[16]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  for (int i = 0; i < NT / 64; ++i) {
+    a += red[0][i];
+    b += red[1][i];
+  }
+  __syncthreads();
+}
+
 // Loads V (warm start, n x n row-major) or the identity into L.V and, when
-// warm, replaces L.A[0] = G by V^T G V.  Expects L.A[0] = G (padded).
-template <int NP>
+// warm, replaces L.A = G by V^T G V.  Expects L.A = G (padded with zeros).
+template <int NP, int NT>
 __device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < NP * NP; e += 256) {
+  for (int e = tid; e < NP * NP; e += NT) {
     int x = e / NP, y = e % NP;
     L.V[x][y] = (warm && x < n && y < n) ? Vin[x * n + y] : (x == y ? 1.0 : 0.0);
   }
-  for (int e = tid; e < (NP - 1) * (NP / 2); e += 256) {
+  for (int e = tid; e < (NP - 1) * (NP / 2); e += NT) {
     int r = e / (NP / 2), k = e % (NP / 2), p, q;
     jpair(r, k, NP, &p, &q);
     L.tp[r][k] = (unsigned char)p;
@@ -115,7 +145,7 @@ __device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin)
   }
   __syncthreads();
   if (!warm) return;
-  // A[1] = G V, then A[0] = V^T A[1]; 4x4 register blocks per thread.
+  // W = G V, then A = V^T W; 4x4 register blocks per thread.
   const int bx = (tid / (NP / 4)) * 4, by = (tid % (NP / 4)) * 4;
   const bool own = tid < (NP / 4) * (NP / 4);
   double acc[4][4];
@@ -125,14 +155,14 @@ __device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin)
     for (int z = 0; z < n; ++z) {
       double u[4], w[4];
       for (int i = 0; i < 4; ++i) {
-        u[i] = L.A[0][bx + i][z];
+        u[i] = L.A[bx + i][z];
         w[i] = L.V[z][by + i];
       }
       for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
     }
     for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) L.A[1][bx + i][by + j] = acc[i][j];
+      for (int j = 0; j < 4; ++j) L.W[bx + i][by + j] = acc[i][j];
   }
   __syncthreads();
   if (own) {
@@ -142,125 +172,121 @@ __device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin)
       double u[4], w[4];
       for (int i = 0; i < 4; ++i) {
         u[i] = L.V[z][bx + i];
-        w[i] = L.A[1][z][by + i];
+        w[i] = L.W[z][by + i];
       }
       for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
     }
     for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) L.A[0][bx + i][by + j] = acc[i][j];
+      for (int j = 0; j < 4; ++j) L.A[bx + i][by + j] = acc[i][j];
   }
   __syncthreads();
-  for (int e = tid; e < NP * NP; e += 256) {
+  for (int e = tid; e < NP * NP; e += NT) {
     int x = e / NP, y = e % NP;
     if (x < y) {
-      double m = 0.5 * (L.A[0][x][y] + L.A[0][y][x]);
-      L.A[0][x][y] = m;
-      L.A[0][y][x] = m;
+      double m = 0.5 * (L.A[x][y] + L.A[y][x]);
+      L.A[x][y] = m;
+      L.A[y][x] = m;
     }
   }
   __syncthreads();
 }
 
-// Cyclic two-sided Jacobi on L.A[0] (n x n padded to NP, symmetric),
+// Cyclic two-sided Jacobi on L.A (n x n padded to NP, symmetric),
 // accumulating rotations into L.V.  Each round applies NP/2 disjoint
-// rotations (round-robin ordering): every wave computes the round's
-// rotations in its lanes and hands them out by shuffles; every 2x2 block
-// is read from one buffer and written to the other, so a round needs a
-// single barrier.  A rotation is skipped when |a_pq| <= 1e-17 (|a_pp| +
-// |a_qq|); a round with no rotation left is skipped as a whole.  Stops
-// when sum_{p != q} a_pq^2 <= 1e-26 sum_p a_pp^2.  Returns the index of
-// the buffer holding the result; *conv tells whether it converged.
-template <int NP>
-__device__ int jacobi_core(JacLds<NP>& L, bool* conv, int* sweeps_used = nullptr) {
+// rotations (round-robin ordering): their angles are computed by the first
+// NP/2 threads and staged in LDS, then every 2x2 block and every row pair of
+// V is updated in place by one thread.
+//
+// Only the leading `rtop` eigenpairs are wanted, so the stopping test looks
+// at the rows of the rtop largest diagonal entries: it stops when their
+// off-diagonal mass is below 1e-20 of their diagonal mass (an eigenvector
+// error below 1e-10 / relative gap).  Returns the number of sweeps run;
+// *conv tells whether the test passed.
+template <int NP, int NT>
+__device__ int jacobi_core(JacLds<NP>& L, int n, int rtop, bool* conv, double tol2 = kOffTol2) {
   constexpr int PAIRS = NP / 2, ROUNDS = NP - 1;
-  constexpr int BITER = (PAIRS * PAIRS + 255) / 256, VITER = (NP * PAIRS + 255) / 256;
-  const int tid = threadIdx.x, lane = tid & 63;
-  int cur = 0;
+  const int tid = threadIdx.x;
   *conv = false;
-  for (int sweep = 0; sweep <= kMaxSweeps; ++sweep) {
+  int sweep = 0;
+  for (; sweep <= kMaxSweeps; ++sweep) {
     double off = 0.0, dg = 0.0;
-    for (int e = tid; e < NP * NP; e += 256) {
-      int x = e / NP, y = e % NP;
-      double v = L.A[cur][x][y];
-      if (x == y) dg += v * v;
-      else off += v * v;
+    if (tid < n) {
+      double dx = L.A[tid][tid];
+      int rank = 0;
+      for (int y = 0; y < n; ++y) {
+        double dy = L.A[y][y];
+        rank += (dy > dx) || (dy == dx && y < tid);
+      }
+      if (rank < rtop) {
+        dg = dx * dx;
+        for (int y = 0; y < n; ++y)
+          if (y != tid) off += L.A[tid][y] * L.A[tid][y];
+      }
     }
-    block_sum2(off, dg, L.red);
-    *conv = (off <= kOffTol2 * dg) || dg == 0.0;
-    if (sweeps_used) *sweeps_used = sweep;
+    block_sum2n<NT>(off, dg, L.red);
+    *conv = (off <= tol2 * dg) || dg == 0.0;
     if (*conv || sweep == kMaxSweeps) break;
     for (int r = 0; r < ROUNDS; ++r) {
-      double c = 1.0, sn = 0.0, t = 0.0;
-      int act = 0;
-      if (lane < PAIRS) {
-        int p = L.tp[r][lane], q = L.tq[r][lane];
-        double apq = L.A[cur][p][q], app = L.A[cur][p][p], aqq = L.A[cur][q][q];
+      if (tid < PAIRS) {
+        int p = L.tp[r][tid], q = L.tq[r][tid];
+        double apq = L.A[p][q], app = L.A[p][p], aqq = L.A[q][q];
+        double c = 1.0, sn = 0.0, t = 0.0;
         if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * (fabs(app) + fabs(aqq))) {
           double th = (aqq - app) / (2.0 * apq);
           t = fabs(th) > 1e150 ? 0.5 / th : copysign(1.0, th) / (fabs(th) + sqrt(fma(th, th, 1.0)));
           c = rsqrt(fma(t, t, 1.0));
           sn = t * c;
-          act = 1;
         }
-      }
-      if (__ballot(act) == 0ull) continue;   // same decision in every wave
-      const int nxt = cur ^ 1;
-      for (int j = 0; j < BITER; ++j) {
-        int blk = tid + 256 * j;
-        bool ok = blk < PAIRS * PAIRS;
-        int ia = ok ? blk / PAIRS : 0, ib = ok ? blk % PAIRS : 0;
-        double ca = __shfl(c, ia, 64), sa = __shfl(sn, ia, 64), ta = __shfl(t, ia, 64);
-        double cb = __shfl(c, ib, 64), sb = __shfl(sn, ib, 64);
-        if (ok) {
-          int pa = L.tp[r][ia], qa = L.tq[r][ia], pb = L.tp[r][ib], qb = L.tq[r][ib];
-          if (ia == ib) {
-            double apq = L.A[cur][pa][qa];
-            L.A[nxt][pa][pa] = L.A[cur][pa][pa] - ta * apq;
-            L.A[nxt][qa][qa] = L.A[cur][qa][qa] + ta * apq;
-            L.A[nxt][pa][qa] = 0.0;
-            L.A[nxt][qa][pa] = 0.0;
-          } else {
-            double w11 = L.A[cur][pa][pb], w12 = L.A[cur][pa][qb];
-            double w21 = L.A[cur][qa][pb], w22 = L.A[cur][qa][qb];
-            double r11 = ca * w11 - sa * w21, r12 = ca * w12 - sa * w22;
-            double r21 = sa * w11 + ca * w21, r22 = sa * w12 + ca * w22;
-            L.A[nxt][pa][pb] = cb * r11 - sb * r12;
-            L.A[nxt][pa][qb] = sb * r11 + cb * r12;
-            L.A[nxt][qa][pb] = cb * r21 - sb * r22;
-            L.A[nxt][qa][qb] = sb * r21 + cb * r22;
-          }
-        }
-      }
-      for (int j = 0; j < VITER; ++j) {
-        int it = tid + 256 * j;
-        bool ok = it < NP * PAIRS;
-        int x = ok ? it / PAIRS : 0, ib = ok ? it % PAIRS : 0;
-        double cb = __shfl(c, ib, 64), sb = __shfl(sn, ib, 64);
-        if (ok) {
-          int pb = L.tp[r][ib], qb = L.tq[r][ib];
-          double v1 = L.V[x][pb], v2 = L.V[x][qb];
-          L.V[x][pb] = cb * v1 - sb * v2;
-          L.V[x][qb] = sb * v1 + cb * v2;
-        }
+        L.rc[tid] = c;
+        L.rs[tid] = sn;
+        L.rt[tid] = t;
       }
       __syncthreads();
-      cur = nxt;
+      for (int blk = tid; blk < PAIRS * PAIRS; blk += NT) {
+        int ia = blk / PAIRS, ib = blk % PAIRS;
+        int pa = L.tp[r][ia], qa = L.tq[r][ia], pb = L.tp[r][ib], qb = L.tq[r][ib];
+        if (ia == ib) {
+          double ta = L.rt[ia], apq = L.A[pa][qa];
+          L.A[pa][pa] -= ta * apq;
+          L.A[qa][qa] += ta * apq;
+          L.A[pa][qa] = 0.0;
+          L.A[qa][pa] = 0.0;
+        } else {
+          double ca = L.rc[ia], sa = L.rs[ia], cb = L.rc[ib], sb = L.rs[ib];
+          double w11 = L.A[pa][pb], w12 = L.A[pa][qb], w21 = L.A[qa][pb], w22 = L.A[qa][qb];
+          double r11 = ca * w11 - sa * w21, r12 = ca * w12 - sa * w22;
+          double r21 = sa * w11 + ca * w21, r22 = sa * w12 + ca * w22;
+          L.A[pa][pb] = cb * r11 - sb * r12;
+          L.A[pa][qb] = sb * r11 + cb * r12;
+          L.A[qa][pb] = cb * r21 - sb * r22;
+          L.A[qa][qb] = sb * r21 + cb * r22;
+        }
+      }
+      for (int it = tid; it < NP * PAIRS; it += NT) {
+        int x = it / PAIRS, ib = it % PAIRS;
+        int pb = L.tp[r][ib], qb = L.tq[r][ib];
+        double cb = L.rc[ib], sb = L.rs[ib];
+        double v1 = L.V[x][pb], v2 = L.V[x][qb];
+        L.V[x][pb] = cb * v1 - sb * v2;
+        L.V[x][qb] = sb * v1 + cb * v2;
+      }
+      __syncthreads();
     }
   }
-  return cur;
+  return sweep;
 }
 
 // Ranks of the eigenvalues (descending, ties by index) into L.rk; writes
 // lam[rank] and Vout[row * n + rank] (n x n) when given.
-template <int NP>
-__device__ void jacobi_sort_store(JacLds<NP>& L, int cur, int n, double* lam, double* Vout) {
+template <int NP, int NT>
+__device__ void jacobi_sort_store(JacLds<NP>& L, int n, double* lam, double* Vout) {
   const int tid = threadIdx.x;
   if (tid < n) {
-    double lx = L.A[cur][tid][tid];
+    double lx = L.A[tid][tid];
     int rank = 0;
     for (int y = 0; y < n; ++y) {
-      double ly = L.A[cur][y][y];
+      double ly = L.A[y][y];
       rank += (ly > lx) || (ly == lx && y < tid);
     }
     L.rk[tid] = rank;
@@ -268,27 +294,27 @@ __device__ void jacobi_sort_store(JacLds<NP>& L, int cur, int n, double* lam, do
   }
   __syncthreads();
   if (Vout)
-    for (int e = tid; e < n * NP; e += 256) {
+    for (int e = tid; e < n * NP; e += NT) {
       int row = e / NP, x = e % NP;
       if (x < n) Vout[row * n + L.rk[x]] = L.V[row][x];
     }
 }
 
-template <int NP>
-__global__ __launch_bounds__(256) void k_jacobi_small(JacArgs a) {
+template <int NP, int NT>
+__global__ __launch_bounds__(NT) void k_jacobi_small(JacArgs a) {
   if (a.s.skip()) return;
   __shared__ JacLds<NP> L;
   const int n = (int)a.n, tid = threadIdx.x;
   const bool warm = (*a.tag == a.tagval);
-  for (int e = tid; e < NP * NP; e += 256) {
+  for (int e = tid; e < NP * NP; e += NT) {
     int x = e / NP, y = e % NP;
-    L.A[0][x][y] = (x < n && y < n) ? a.G[x * n + y] : 0.0;
+    L.A[x][y] = (x < n && y < n) ? a.G[x * n + y] : 0.0;
   }
   __syncthreads();
-  jacobi_setup<NP>(L, n, warm, a.V);
+  jacobi_setup<NP, NT>(L, n, warm, a.V);
   bool conv;
-  int cur = jacobi_core<NP>(L, &conv);
-  jacobi_sort_store<NP>(L, cur, n, a.lam, a.V);
+  jacobi_core<NP, NT>(L, n, a.rtop, &conv, a.tol2);
+  jacobi_sort_store<NP, NT>(L, n, a.lam, a.V);
   if (tid == 0) {
     *a.tag = a.tagval;
     if (!conv) atomicCAS(a.s.st, 0, MACH_ENOCONV);
@@ -316,31 +342,28 @@ struct SolveArgs {
   Status st;
 };
 
-template <int NP>
-__global__ __launch_bounds__(256) void k_mode_solve(SolveArgs a) {
+template <int NP, int NT>
+__global__ __launch_bounds__(NT) void k_mode_solve(SolveArgs a) {
   if (a.st.skip()) return;
   __shared__ JacLds<NP> L;
   __shared__ double sgn[16];
+  __shared__ int col_of_rank[16];
   const int n = (int)a.s, tid = threadIdx.x;
   const uint32_t n2 = a.s * a.s;
-  for (int e = tid; e < NP * NP; e += 256) {
+  for (int e = tid; e < NP * NP; e += NT) {
     int x = e / NP, y = e % NP;
     double g = 0.0;
     if (x < n && y < n)
       for (uint32_t c = 0; c < a.nchunk; ++c) g += a.part[(size_t)c * n2 + x * n + y];
-    L.A[0][x][y] = g;
+    L.A[x][y] = g;
   }
   __syncthreads();
   const bool warm = (*a.tag == a.tagval);
-  jacobi_setup<NP>(L, n, warm, a.V);
+  jacobi_setup<NP, NT>(L, n, warm, a.V);
   bool conv;
-  int used = 0;
-  int cur = jacobi_core<NP>(L, &conv, &used);
-  jacobi_sort_store<NP>(L, cur, n, a.lam, a.V);
+  int used = jacobi_core<NP, NT>(L, n, (int)a.R, &conv);
+  jacobi_sort_store<NP, NT>(L, n, a.lam, a.V);
   if (tid == 0 && a.stats) *a.stats = used + (warm ? 1000 : 0);
-  __syncthreads();
-  // rk maps eigen index -> rank; invert it for the top R columns
-  __shared__ int col_of_rank[16];
   if (tid < n && L.rk[tid] < (int)a.R) col_of_rank[L.rk[tid]] = tid;
   __syncthreads();
   if (tid == 0) {
@@ -349,16 +372,16 @@ __global__ __launch_bounds__(256) void k_mode_solve(SolveArgs a) {
   }
   if (a.kside) {
     if (tid == 0) {
-      double l0 = L.A[cur][col_of_rank[0]][col_of_rank[0]];
-      double lr = L.A[cur][col_of_rank[a.R - 1]][col_of_rank[a.R - 1]];
+      double l0 = L.A[col_of_rank[0]][col_of_rank[0]];
+      double lr = L.A[col_of_rank[a.R - 1]][col_of_rank[a.R - 1]];
       if (!(lr > 1e-13 * l0)) atomicCAS(a.st.st, 0, MACH_EDEGENERATE);
     }
-    for (int e = tid; e < n * 16; e += 256) {
+    for (int e = tid; e < n * 16; e += NT) {
       int x = e >> 4, r = e & 15;
       double v = 0.0;
       if (r < (int)a.R) {
         int col = col_of_rank[r];
-        v = L.V[x][col] / sqrt(fmax(L.A[cur][col][col], 1e-300));
+        v = L.V[x][col] / sqrt(fmax(L.A[col][col], 1e-300));
       }
       a.M[e] = v;
     }
@@ -378,7 +401,7 @@ __global__ __launch_bounds__(256) void k_mode_solve(SolveArgs a) {
     sgn[tid] = val < 0.0 ? -1.0 : 1.0;
   }
   __syncthreads();
-  for (int e = tid; e < n * 16; e += 256) {
+  for (int e = tid; e < n * 16; e += NT) {
     int x = e >> 4, r = e & 15;
     double v = r < (int)a.R ? sgn[r] * L.V[x][col_of_rank[r]] : 0.0;
     if (r < (int)a.R) a.Aout[(size_t)x * a.R + r] = v;
@@ -489,27 +512,39 @@ __global__ __launch_bounds__(256) void k_chol_apply_tall(double* __restrict__ Aw
 #pragma unroll
     for (int r = 0; r < 16; ++r) Aw[(size_t)i * 16 + r] = out[r];
   }
-  // column maxima over this workgroup's rows (value, then lowest row)
+  // column maxima over this workgroup's rows (value, then lowest row):
+  // butterfly within each wave, then the 4 wave results in order.
+  const int lane = tid & 63, wv = tid >> 6;
   for (int r = 0; r < 16; ++r) {
-    bv[tid] = i < I ? fabs(out[r]) : -1.0;
-    bi[tid] = i;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) {
-        double v2 = bv[tid + o];
-        uint32_t i2 = bi[tid + o];
-        if (v2 > bv[tid] || (v2 == bv[tid] && i2 < bi[tid])) {
-          bv[tid] = v2;
-          bi[tid] = i2;
-        }
+    double v = i < I ? fabs(out[r]) : -1.0;
+    uint32_t ix = i;
+    for (int m = 1; m < 64; m <<= 1) {
+      double v2 = __shfl_xor(v, m, 64);
+      uint32_t i2 = __shfl_xor(ix, m, 64);
+      if (v2 > v || (v2 == v && i2 < ix)) {
+        v = v2;
+        ix = i2;
       }
-      __syncthreads();
     }
-    if (tid == 0) {
-      pv[blockIdx.x * 16 + r] = bv[0];
-      pi[blockIdx.x * 16 + r] = bi[0];
+    if (lane == 0) {
+      bv[wv * 16 + r] = v;
+      bi[wv * 16 + r] = ix;
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  if (tid < 16) {
+    double v = bv[tid];
+    uint32_t ix = bi[tid];
+    for (int w2 = 1; w2 < 4; ++w2) {
+      double v2 = bv[w2 * 16 + tid];
+      uint32_t i2 = bi[w2 * 16 + tid];
+      if (v2 > v || (v2 == v && i2 < ix)) {
+        v = v2;
+        ix = i2;
+      }
+    }
+    pv[blockIdx.x * 16 + tid] = v;
+    pi[blockIdx.x * 16 + tid] = ix;
   }
 }
 
@@ -517,50 +552,44 @@ __global__ __launch_bounds__(256) void k_chol_apply_tall(double* __restrict__ Aw
 // Dense float64 helpers for the subspace solver and CholeskyQR2
 // ---------------------------------------------------------------------------
 
-// C[M x N] = A[M x K] * B[K x N] (row-major, leading dims), N <= 64.
+// C[M x N] = A[M x K] * B[K x N] (row-major, leading dims), N <= 64.  A
+// workgroup owns 16 rows; thread (row, column group of 4).
 __global__ __launch_bounds__(256) void k_gemm64(const double* __restrict__ A, uint32_t lda,
                                                 const double* __restrict__ B, uint32_t ldb,
                                                 double* __restrict__ C, uint32_t ldc, uint32_t M,
                                                 uint32_t K, uint32_t N, Status s) {
   if (s.skip()) return;
-  __shared__ double As[64][33];
-  __shared__ double Bs[32][65];
+  __shared__ double As[16][65];
+  __shared__ double Bs[64][65];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const uint32_t m0 = blockIdx.x * 64;
-  double acc[4][4] = {};
-  for (uint32_t k0 = 0; k0 < K; k0 += 32) {
-    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-      int r = e >> 5, c = e & 31;
+  const uint32_t m0 = blockIdx.x * 16;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (uint32_t k0 = 0; k0 < K; k0 += 64) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      int r = e >> 6, c = e & 63;
       uint32_t m = m0 + r, k = k0 + c;
       As[r][c] = (m < M && k < K) ? A[(size_t)m * lda + k] : 0.0;
     }
-    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
       int r = e >> 6, c = e & 63;
       uint32_t k = k0 + r;
       Bs[r][c] = (k < K && (uint32_t)c < N) ? B[(size_t)k * ldb + c] : 0.0;
     }
     __syncthreads();
-    for (int kk = 0; kk < 32; ++kk) {
-      double u[4], w[4];
+#pragma unroll 8
+    for (int kk = 0; kk < 64; ++kk) {
+      double u = As[ty][kk];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        u[i] = As[ty * 4 + i][kk];
-        w[i] = Bs[kk][tx * 4 + i];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
+      for (int j = 0; j < 4; ++j) acc[j] = fma(u, Bs[kk][tx * 4 + j], acc[j]);
     }
     __syncthreads();
   }
+  uint32_t m = m0 + ty;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      uint32_t m = m0 + ty * 4 + i, n = tx * 4 + j;
-      if (m < M && n < N) C[(size_t)m * ldc + n] = acc[i][j];
-    }
+  for (int j = 0; j < 4; ++j) {
+    uint32_t n = tx * 4 + j;
+    if (m < M && n < N) C[(size_t)m * ldc + n] = acc[j];
+  }
 }
 
 // part[chunk][x][y] = sum over the chunk's rows m of A[m][x] * B[m][y]  (x, y < n <= 64)
@@ -663,6 +692,47 @@ __global__ __launch_bounds__(256) void k_cholqr_apply(double* __restrict__ X, ui
     }
     if (lane < (int)n) X[(size_t)m * ldx + lane] = x;
   }
+}
+
+// B = L^{-T} for the Cholesky factor L of S + shift * tr(S) / n * I
+// (n <= 64), so that X B has orthonormal columns when S = X^T X.  One
+// wave: lane x owns row x during the factorisation and column x of L^{-1}
+// during the forward substitution.
+__global__ __launch_bounds__(64) void k_chol_inv(const double* __restrict__ S, uint32_t n, double shift,
+                                                 double* __restrict__ B, Status s) {
+  if (s.skip()) return;
+  __shared__ double Lm[64][65];
+  __shared__ double Li[64][65];
+  const int x = threadIdx.x;
+  double tr = 0.0;
+  for (uint32_t i = 0; i < n; ++i) tr += S[i * n + i];
+  for (uint32_t j = 0; j < 64; ++j) Lm[x][j] = (x < (int)n && j < n) ? S[x * n + j] : 0.0;
+  if (x < (int)n) Lm[x][x] += shift * tr / n;
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t j = 0; j < n; ++j) {
+    if (x == (int)j) Lm[j][j] = Lm[j][j] > 1e-300 ? sqrt(Lm[j][j]) : 1.0;
+    __builtin_amdgcn_wave_barrier();
+    double d = Lm[j][j];
+    if (x > (int)j && x < (int)n) Lm[x][j] /= d;
+    __builtin_amdgcn_wave_barrier();
+    if (x > (int)j && x < (int)n) {
+      double lxj = Lm[x][j];
+      for (uint32_t k = j + 1; k <= (uint32_t)x; ++k) Lm[x][k] -= lxj * Lm[k][j];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (uint32_t i = 0; i < 64; ++i) Li[i][x] = 0.0;
+  __builtin_amdgcn_wave_barrier();
+  if (x < (int)n)
+    for (uint32_t i = x; i < n; ++i) {
+      double v = (i == (uint32_t)x) ? 1.0 : 0.0;
+      for (uint32_t k = x; k < i; ++k) v -= Lm[i][k] * Li[k][x];
+      Li[i][x] = v / Lm[i][i];
+    }
+  __builtin_amdgcn_wave_barrier();
+  // B[k][j] = Li[j][k]
+  if (x < (int)n)
+    for (uint32_t j = 0; j < n; ++j) B[x * n + j] = Li[j][x];
 }
 
 // Deterministic start block for the subspace iteration (hash of position).
@@ -1001,12 +1071,12 @@ void cholqr2(const Ctx& c, double* X, uint32_t ldx, uint32_t M, uint32_t n, bool
 
 void gemm(const Ctx& c, const double* A, uint32_t lda, const double* B, uint32_t ldb, double* C,
           uint32_t ldc, uint32_t M, uint32_t K, uint32_t N, bool with_done) {
-  hipLaunchKernelGGL(k_gemm64, dim3(cdiv(M, 64)), dim3(256), 0, c.st, A, lda, B, ldb, C, ldc, M, K,
+  hipLaunchKernelGGL(k_gemm64, dim3(cdiv(M, 16)), dim3(256), 0, c.st, A, lda, B, ldb, C, ldc, M, K,
                      N, c.stat(with_done));
 }
 
 void jacobi(const Ctx& c, const double* G, uint32_t n, double* V, double* lam, int32_t* tag,
-            int32_t tagval, bool with_done) {
+            int32_t tagval, bool with_done, int rtop, double tol2 = kOffTol2) {
   JacArgs a;
   a.G = G;
   a.n = n;
@@ -1014,42 +1084,78 @@ void jacobi(const Ctx& c, const double* G, uint32_t n, double* V, double* lam, i
   a.lam = lam;
   a.tag = tag;
   a.tagval = tagval;
+  a.rtop = rtop;
+  a.tol2 = tol2;
   a.s = c.stat(with_done);
   if (n <= 16)
-    hipLaunchKernelGGL(k_jacobi_small<16>, dim3(1), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((k_jacobi_small<16, 256>), dim3(1), dim3(256), 0, c.st, a);
   else if (n <= 32)
-    hipLaunchKernelGGL(k_jacobi_small<32>, dim3(1), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((k_jacobi_small<32, 256>), dim3(1), dim3(256), 0, c.st, a);
   else
-    hipLaunchKernelGGL(k_jacobi_small<64>, dim3(1), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((k_jacobi_small<64, 1024>), dim3(1), dim3(1024), 0, c.st, a);
+}
+
+// X (M x n, ld kBlock) <- X with orthonormal columns, by two Cholesky-QR
+// passes (the first shifted by 1e-15 tr(S) / n); Y is scratch of X's size.
+void orthonormalise(const Ctx& c, double* X, double* Y, uint32_t M, uint32_t n, bool with_done) {
+  Status sd = c.stat(with_done);
+  uint32_t nchunk = cdiv(M, 256);
+  if (nchunk > 64) nchunk = 64;
+  uint32_t rows = cdiv(M, nchunk);
+  double* S = c.d(c.SL->small);
+  double* B = c.d(c.SL->H);
+  double* src = X;
+  double* dst = Y;
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, src, kBlock, src, kBlock, M, n,
+                       rows, c.d(c.SL->part), sd);
+    hipLaunchKernelGGL(k_small_reduce, dim3(cdiv(n * n, 256)), dim3(256), 0, c.st, c.d(c.SL->part),
+                       nchunk, n * n, S, sd);
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, c.st, S, n, pass == 0 ? 1e-15 : 0.0, B, sd);
+    gemm(c, src, kBlock, B, n, dst, kBlock, M, n, n, with_done);
+    double* t = src;
+    src = dst;
+    dst = t;
+  }
+  // after two passes the result is back in X
 }
 
 // Top eigenpairs of the s x s matrix G (s > 64) by block subspace iteration
-// with Rayleigh-Ritz every 4 steps.  Q (s x 64, ld 64) holds the block (warm
-// start if *tag == tagval); on return its first columns are the Ritz
-// vectors, lam (64) the Ritz values, descending.
+// on b = min(64, max(32, 2R rounded up to 16)) columns: two multiplications
+// by G per orthonormalisation, Rayleigh-Ritz every 8 steps and at the end,
+// stopping once the top R Ritz residuals are below 1e-10 of the largest
+// Ritz value.  Q (s x 64, ld 64) holds the block (warm start if *tag ==
+// tagval); on return its first R columns are the Ritz vectors and lam the
+// Ritz values, descending.
 void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double* Q, double* lam,
                    int32_t* tag, int32_t tagval, int maxit, int32_t* stat_it) {
-  const uint32_t b = s < kBlock ? s : kBlock;
+  uint32_t b = 2 * R;
+  b = b < 32 ? 32 : (b + 15) / 16 * 16;
+  if (b > kBlock) b = kBlock;
+  if (b > s) b = s;
   int32_t* tags = c.tags();
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagDone, 0);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagRR, 0);
   hipLaunchKernelGGL(k_ss_init, dim3(cdiv((uint64_t)s * b, 256)), dim3(256), 0, c.st, Q, kBlock, s,
                      b, tag, tagval, c.stat());
-  cholqr2(c, Q, kBlock, s, b, false);
   double* Z = c.d(c.SL->Zs);
   double* Z2 = c.d(c.SL->Z2s);
   double* Qr = c.d(c.SL->Qrs);
   double* H = c.d(c.SL->H);
   double* VH = c.d(c.SL->VH);
   double* lamH = c.d(c.SL->lamH);
+  orthonormalise(c, Q, Z, s, b, false);
   Status sd = c.stat(true);
+  const uint32_t nb = cdiv((uint64_t)s * kBlock, 256);
   for (int it = 0; it < maxit; ++it) {
+    const bool last = it == maxit - 1;
+    const bool rr = (it % 8 == 7) || last;
     gemm(c, G, s, Q, kBlock, Z, kBlock, s, s, b, true);
-    cholqr2(c, Z, kBlock, s, b, true);
-    hipLaunchKernelGGL(k_copy64, dim3(cdiv((uint64_t)s * kBlock, 256)), dim3(256), 0, c.st, Z, Q,
-                       s * kBlock, sd);
-    bool last = it == maxit - 1;
-    if (it % 4 == 3 || last) {
+    if (it % 2 == 1 || rr) {
+      orthonormalise(c, Z, Z2, s, b, true);
+    }
+    hipLaunchKernelGGL(k_copy64, dim3(nb), dim3(256), 0, c.st, Z, Q, s * kBlock, sd);
+    if (rr) {
       gemm(c, G, s, Q, kBlock, Z, kBlock, s, s, b, true);
       uint32_t nchunk = cdiv(s, 256);
       if (nchunk > 64) nchunk = 64;
@@ -1058,17 +1164,42 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
                          rows, c.d(c.SL->part), sd);
       hipLaunchKernelGGL(k_small_reduce, dim3(cdiv(b * b, 256)), dim3(256), 0, c.st, c.d(c.SL->part),
                          nchunk, b * b, H, sd);
-      jacobi(c, H, b, VH, lamH, tags + kTagRR, 0x52520000 | (int32_t)b, true);
+      jacobi(c, H, b, VH, lamH, tags + kTagRR, 0x52520000 | (int32_t)b, true, (int)R, 1e-28);
       gemm(c, Q, kBlock, VH, b, Qr, kBlock, s, b, b, true);
       gemm(c, Z, kBlock, VH, b, Z2, kBlock, s, b, b, true);
-      hipLaunchKernelGGL(k_copy64, dim3(cdiv((uint64_t)s * kBlock, 256)), dim3(256), 0, c.st, Qr, Q,
-                         s * kBlock, sd);
+      hipLaunchKernelGGL(k_copy64, dim3(nb), dim3(256), 0, c.st, Qr, Q, s * kBlock, sd);
       hipLaunchKernelGGL(k_copy64, dim3(1), dim3(256), 0, c.st, lamH, lam, b, sd);
-      hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, Z2, Qr, kBlock, s, lamH, R, 1e-12,
+      hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, Z2, Qr, kBlock, s, lamH, R, 1e-10,
                          tags + kTagDone, last ? 1 : 0, stat_it, it, c.stat(true));
     }
   }
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tag, tagval);
+}
+
+__global__ __launch_bounds__(256) void k_ata16_partial(const double* __restrict__ Aw, uint32_t I,
+                                                       double* __restrict__ part, Status s) {
+  if (s.skip()) return;
+  __shared__ double rows[256][17];
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) rows[threadIdx.x][r] = i < I ? Aw[(size_t)i * 16 + r] : 0.0;
+  __syncthreads();
+  const int x = threadIdx.x >> 4, y = threadIdx.x & 15;
+  double g = 0.0;
+  for (int t = 0; t < 256; ++t) g = fma(rows[t][x], rows[t][y], g);
+  part[(size_t)blockIdx.x * 256 + threadIdx.x] = g;
+}
+
+// Aw (I x 16, nearly orthonormal columns) -> one Cholesky-QR pass, the sign
+// rule, and the float64 / float32 stores.
+void finish_factor(const Ctx& c, uint32_t I, uint32_t R, double* Aout, float* af) {
+  uint32_t nwg = cdiv(I, 256);
+  double* part = c.d(c.SL->part);
+  hipLaunchKernelGGL(k_ata16_partial, dim3(nwg), dim3(256), 0, c.st, c.d(c.SL->Aw), I, part, c.stat());
+  hipLaunchKernelGGL(k_chol_apply_tall, dim3(nwg), dim3(256), 0, c.st, c.d(c.SL->Aw), I, R, part, nwg,
+                     c.d(c.SL->pv), (uint32_t*)(c.ws + c.SL->pi), c.stat());
+  hipLaunchKernelGGL(k_sign_store, dim3(cdiv((uint64_t)I * 16, 256)), dim3(256), 0, c.st, c.d(c.SL->Aw),
+                     I, R, c.d(c.SL->pv), (const uint32_t*)(c.ws + c.SL->pi), nwg, Aout, af, c.stat());
 }
 
 // Sign rule and stores from Aw (I x 16 float64).
@@ -1104,6 +1235,12 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     if (e != hipSuccess) return e;
     SolveArgs a;
     a.part = c.d(SL.Gpart);
+    if (nchunk > 4) {
+      hipLaunchKernelGGL(k_small_reduce, dim3(cdiv(m.s * m.s, 256)), dim3(256), 0, st, c.d(SL.Gpart),
+                         nchunk, m.s * m.s, c.d(SL.G), c.stat());
+      a.part = c.d(SL.G);
+      nchunk = 1;
+    }
     a.nchunk = nchunk;
     a.s = m.s;
     a.I = m.I;
@@ -1119,11 +1256,11 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     a.stats = (int32_t*)(ws + SL.status + 96) + k;
     a.st = c.stat();
     if (m.s <= 16)
-      hipLaunchKernelGGL(k_mode_solve<16>, dim3(1), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_mode_solve<16, 256>), dim3(1), dim3(256), 0, st, a);
     else if (m.s <= 32)
-      hipLaunchKernelGGL(k_mode_solve<32>, dim3(1), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_mode_solve<32, 256>), dim3(1), dim3(256), 0, st, a);
     else
-      hipLaunchKernelGGL(k_mode_solve<64>, dim3(1), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_mode_solve<64, 1024>), dim3(1), dim3(1024), 0, st, a);
     if (m.kside) {
       uint32_t nwg = cdiv(m.I, 256);
       double* part = c.d(SL.part);
@@ -1145,7 +1282,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
   if (m.s <= (uint32_t)kSmallEig) {
     V = c.d(m.V);
     ldv = m.s;
-    jacobi(c, G, m.s, V, c.d(m.lam), c.tags() + k, tagval, false);
+    jacobi(c, G, m.s, V, c.d(m.lam), c.tags() + k, tagval, false, (int)m.R);
   } else {
     V = c.d(m.Q64);
     ldv = kBlock;
@@ -1157,7 +1294,8 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     hipLaunchKernelGGL(k_backproject_dense, dim3(cdiv(m.I, 256)), dim3(256), 0, st,
                        (const float*)(ws + m.ybuf), m.I, m.Q, J, make_fastdiv(m.Q), V, ldv,
                        c.d(m.lam), m.R, c.d(SL.Aw), c.stat());
-    cholqr2(c, c.d(SL.Aw), 16, m.I, m.R, false);
+    finish_factor(c, m.I, m.R, A_out, (float*)(ws + SL.af[k]));
+    return hipGetLastError();
   } else {
     hipLaunchKernelGGL(k_take_cols, dim3(cdiv((uint64_t)m.I * 16, 256)), dim3(256), 0, st, V, ldv,
                        m.I, m.R, c.d(SL.Aw), c.stat());
@@ -1169,7 +1307,8 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
 hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
                              char* ws, int n, int R, double* A_out, hipStream_t st) {
   Ctx c{&SL, ws, sp.hdr, st};
-  hipError_t e = launch_gram_xhat(si, sp, SL, ws, n, st);
+  hipError_t e = sparse_tail_gram_ok(si, SL, n) ? launch_gram_tail_sparse(si, sp, SL, ws, st)
+                                                : launch_gram_xhat(si, sp, SL, ws, n, st);
   if (e != hipSuccess) return e;
   const uint32_t s = SL.hosvd_s[n];
   const double* G = c.d(SL.G);
@@ -1180,23 +1319,25 @@ hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const So
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, tagc, 0);
   if (s <= (uint32_t)kSmallEig) {
     ldv = s;
-    jacobi(c, G, s, V, lam, tagc, 0x48000000 | (int32_t)s, false);
+    jacobi(c, G, s, V, lam, tagc, 0x48000000 | (int32_t)s, false, R);
   } else {
     ldv = kBlock;
-    subspace_topk(c, G, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 80,
+    subspace_topk(c, G, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 96,
                   (int32_t*)(ws + SL.status + 128) + n);
   }
   const uint32_t I = si.dims[n];
   if (SL.hosvd_kside[n] && n == si.d - 1 && si.h == si.d - 1) {
     hipLaunchKernelGGL(k_backproject_cols, dim3(cdiv(I, 4)), dim3(256), 0, st, sp.coo_t, sp.colptr, I,
                        si.fMT, V, ldv, lam, (uint32_t)R, c.d(SL.Aw), c.stat());
-    cholqr2(c, c.d(SL.Aw), 16, I, (uint32_t)R, false);
+    finish_factor(c, I, (uint32_t)R, A_out, (float*)(ws + SL.af[n]));
+    return hipGetLastError();
   } else if (SL.hosvd_kside[n]) {
     uint32_t J = si.N / I;
     hipLaunchKernelGGL(k_backproject_xhat, dim3(cdiv(I, 256)), dim3(256), 0, st, sp.bitmap, sp.wrank,
                        sp.coo_l, I, si.stride[n], J, si.fstride[n], V, ldv, lam, (uint32_t)R,
                        c.d(SL.Aw), c.stat());
-    cholqr2(c, c.d(SL.Aw), 16, I, (uint32_t)R, false);
+    finish_factor(c, I, (uint32_t)R, A_out, (float*)(ws + SL.af[n]));
+    return hipGetLastError();
   } else {
     hipLaunchKernelGGL(k_take_cols, dim3(cdiv((uint64_t)I * 16, 256)), dim3(256), 0, st, V, ldv, I,
                        (uint32_t)R, c.d(SL.Aw), c.stat());

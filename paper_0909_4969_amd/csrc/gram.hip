@@ -170,7 +170,61 @@ hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream
   return hipGetLastError();
 }
 
+// Column-side Gram of the sampled unfolding when the mode is the single
+// tail mode: G[r][r'] = sum_c Xhat[r, c] Xhat[r', c] over the CSR rows r
+// (head rows) and tail columns c.  One wave per row r walks the row's
+// entries (c, v) in order; for each, its lanes take the entries (r', v')
+// of CSC column c and add v v' to a float64 accumulator of row r in LDS.
+// The entries of one column have distinct r', so lanes never collide, and
+// every accumulator is summed in column order.
+constexpr uint32_t kSparseGramMaxRows = 2048;
+
+__global__ __launch_bounds__(256) void k_gram_rows_sparse(const Entry* __restrict__ coo_l,
+                                                          const uint32_t* __restrict__ rowptr,
+                                                          const Entry* __restrict__ coo_t,
+                                                          const uint32_t* __restrict__ colptr,
+                                                          uint32_t MH, uint32_t MT, FastDiv fMT,
+                                                          double* __restrict__ G, const SampleHdr* hdr,
+                                                          const int32_t* st_solver) {
+  if (hdr->status != 0 || *st_solver != 0) return;
+  __shared__ double acc[4][kSparseGramMaxRows];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t r = blockIdx.x * 4 + w;
+  double* row = acc[w];
+  for (uint32_t j = lane; j < MH; j += 64) row[j] = 0.0;
+  __builtin_amdgcn_wave_barrier();
+  if (r < MH) {
+    const uint32_t base = r * MT;
+    for (uint32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      Entry a = coo_l[e];
+      const uint32_t c = a.l - base;
+      const double va = (double)a.v;
+      const uint32_t b1 = colptr[c + 1];
+      for (uint32_t f = colptr[c] + lane; f < b1; f += 64) {
+        Entry b = coo_t[f];
+        row[fMT.div(b.l)] += va * (double)b.v;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (r < MH)
+    for (uint32_t j = lane; j < MH; j += 64) G[(size_t)r * MH + j] = row[j];
+}
+
 }  // namespace
+
+bool sparse_tail_gram_ok(const ShapeInfo& si, const SolverLayout& SL, int n) {
+  return SL.hosvd_kside[n] && n == si.d - 1 && si.h == si.d - 1 && si.MH <= kSparseGramMaxRows;
+}
+
+hipError_t launch_gram_tail_sparse(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
+                                   char* ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_rows_sparse, dim3((si.MH + 3) / 4), dim3(256), 0, st, sp.coo_l, sp.rowptr,
+                     sp.coo_t, sp.colptr, si.MH, si.MT, si.fMT, (double*)(ws + SL.G), sp.hdr,
+                     (const int32_t*)(ws + SL.status));
+  return hipGetLastError();
+}
 
 // Gram partials of Y_k (dense float32 view): SL.Gpart[c][X][X], c < *nchunk.
 hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,

@@ -1,5 +1,6 @@
-// Sparse tensor-times-matrix chain (Alg. 2, the "Y <-" line; the n-mode
-// product of Section 2.1) without float atomics.
+// Sparse tensor-times-matrix chain (the projection of the tensor onto all
+// factors but one in Alg. 2; the n-mode product of Section 2.1) without
+// float atomics.
 //
 // A segment is one CSR row (head index r, entries ordered by tail
 // coordinates) or one CSC column (tail index c, entries ordered by head
@@ -8,10 +9,11 @@
 // with at most two contracted modes, evaluated fiber by fiber: along the
 // inner contracted mode it accumulates t = sum v * A_in[i_in, :] (R_in
 // values); when the outer coordinate changes it adds A_out[i_out, :] (x) t
-// into s (R_out x R_in values).  Each segment is split into G contiguous
-// sub-ranges, one per lane, so every lane walks whole fibers in registers;
-// the G partial results are then summed by a fixed xor butterfly.  The
-// result depends only on the data, never on scheduling.
+// into s (R_out x R_in values).  The entries of a segment are dealt to S
+// slots (contiguous sub-ranges when fibers must stay whole, else strided);
+// a slot is R_in / 4 lanes that each own four inner columns.  The S partial
+// results are summed by a fixed xor butterfly, so the result depends only
+// on the data, never on scheduling.
 #include <hip/hip_ext.h>
 
 #include "solver.h"
@@ -32,122 +34,164 @@ struct SpcArgs {
   uint32_t Rin, Rout;
   float* out;              // out[seg * K + kappa]
   uint32_t K;
-  int G;                   // lanes per segment (power of two, 4..64)
+  int G;                   // lanes per segment (power of two, 1..64)
   const SampleHdr* hdr;
   const int32_t* st_solver;
 };
 
+// Entries of the workgroup's segments are staged through LDS in chunks of
+// kStage: one coalesced non-temporal pass over the entry stream (it is read
+// once per sweep, so it should not evict the factor rows from L2).
+constexpr uint32_t kStage = 4096;
+
+// Lane layout: LPE = RI / 4 lanes share one entry, lane `quad` owning inner
+// columns 4*quad .. 4*quad+3, so the LPE lanes gather one contiguous 16*LPE
+// byte factor row together (one cache line per entry instead of one per
+// lane and float4).  The G lanes of a segment form S = G / LPE entry slots.
 template <int NQ, int RI, int RO>
 __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
   if (a.hdr->status != 0 || *a.st_solver != 0) return;
+  constexpr int LPE = RI / 4;
+  static_assert(LPE == 1 || LPE == 2 || LPE == 4, "RI must be 4, 8 or 16");
+  __shared__ uint64_t stage[kStage];
   const int G = a.G;
+  const int S = G / LPE;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
-  const uint32_t seg = blockIdx.x * (256u / G) + threadIdx.x / G;
+  const int quad = gl & (LPE - 1);
+  const int slot = gl / LPE;
+  const uint32_t per = 256u / G;
+  const uint32_t seg0 = blockIdx.x * per;
+  const uint32_t seg = seg0 + threadIdx.x / G;
   const bool valid = seg < a.nseg;
-  uint32_t lo = 0, hi = 0;
+  const uint32_t segN = min(a.nseg, seg0 + per);
+  const uint32_t wg_lo = a.segptr[seg0], wg_hi = a.segptr[segN];
+  uint32_t b0 = 0, b1 = 0;
   if (valid) {
-    uint32_t b0 = a.segptr[seg], b1 = a.segptr[seg + 1];
-    uint32_t L = b1 - b0;
-    lo = b0 + (uint32_t)(((uint64_t)L * gl) / G);
-    hi = b0 + (uint32_t)(((uint64_t)L * (gl + 1)) / G);
+    b0 = a.segptr[seg];
+    b1 = a.segptr[seg + 1];
   }
-  constexpr int NS = (NQ == 2) ? RO * RI : RI;
-  float t[RI];
+  // Two contracted modes: slot walks the contiguous sub-range [lo, hi) (whole
+  // fibers stay in one slot).  One contracted mode: slot takes entries
+  // b0 + slot, b0 + slot + S, ... (order is irrelevant to a plain sum).
+  uint32_t lo = b0, hi = b1;
+  if (NQ == 2) {
+    uint32_t L = b1 - b0;
+    lo = b0 + (uint32_t)(((uint64_t)L * slot) / S);
+    hi = b0 + (uint32_t)(((uint64_t)L * (slot + 1)) / S);
+  }
+  const float4* Ain4 = reinterpret_cast<const float4*>(a.Ain);
+  const float4* Aout4 = reinterpret_cast<const float4*>(a.Aout);
+  constexpr int NS = (NQ == 2) ? RO * 4 : 4;
+  float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
   float s[NS];
-#pragma unroll
-  for (int j = 0; j < RI; ++j) t[j] = 0.f;
 #pragma unroll
   for (int j = 0; j < NS; ++j) s[j] = 0.f;
   uint32_t cur = 0xffffffffu;
   const uint32_t segbase = seg * a.MT;
-  // Batches of U entries: all loads of a batch are issued before any use,
-  // so each lane waits for memory once per batch rather than per entry.
-  constexpr int U = (NS + 4 * RI <= 160) ? 4 : 2;
-  for (uint32_t e0 = lo; e0 < hi; e0 += U) {
-    Entry en[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (e0 + u < hi) {
-        en[u] = a.ent[e0 + u];
-      } else {
-        en[u].l = a.csc ? 0u : segbase;
-        en[u].v = 0.f;
-      }
+  for (uint32_t c0 = wg_lo; c0 < wg_hi; c0 += kStage) {
+    const uint32_t c1 = min(wg_hi, c0 + kStage);
+    __syncthreads();
+    for (uint32_t e = c0 + threadIdx.x; e < c1; e += 256)
+      stage[e - c0] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(a.ent) + e);
+    __syncthreads();
+    uint32_t e_begin, e_step;
+    if (NQ == 2) {
+      e_begin = max(lo, c0);
+      e_step = 1;
+    } else {
+      uint32_t first = b0 + slot;
+      e_begin = first >= c0 ? first : first + ((c0 - first + S - 1) / S) * S;
+      e_step = S;
     }
-    uint32_t iin[U], iout[U];
+    const uint32_t e_end = NQ == 2 ? min(hi, c1) : min(b1, c1);
+    // U entries per step: their factor rows are all requested before any is used.
+    constexpr int U = 2;
+    for (uint32_t e = e_begin; e < e_end; e += U * e_step) {
+      float4 w[U];
+      float v[U];
+      uint32_t io[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      uint32_t x = a.csc ? a.fMT.div(en[u].l) : en[u].l - segbase;
-      iin[u] = x;
-      iout[u] = 0;
-      if (NQ == 2) {
-        uint32_t h = a.flo.div(x);
-        uint32_t l = x - h * a.flo.d;
-        iin[u] = a.inner_is_lo ? l : h;
-        iout[u] = a.inner_is_lo ? h : l;
-      }
-    }
-    float4 w[U][RI / 4];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const float4* ap = reinterpret_cast<const float4*>(a.Ain + (size_t)iin[u] * 16);
-#pragma unroll
-      for (int q = 0; q < RI / 4; ++q) w[u][q] = ap[q];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (NQ == 2 && e0 + u < hi && iout[u] != cur) {
-        if (cur != 0xffffffffu) {
-          const float* ao = a.Aout + (size_t)cur * 16;
-#pragma unroll
-          for (int o = 0; o < RO; ++o) {
-            float wo = ao[o];
-#pragma unroll
-            for (int j = 0; j < RI; ++j) s[o * RI + j] = fmaf(wo, t[j], s[o * RI + j]);
-          }
-#pragma unroll
-          for (int j = 0; j < RI; ++j) t[j] = 0.f;
+      for (int u = 0; u < U; ++u) {
+        const uint32_t eu = e + u * e_step;
+        const bool ok = eu < e_end;
+        const uint64_t en = ok ? stage[eu - c0] : 0ull;
+        const uint32_t el = (uint32_t)en;
+        v[u] = __uint_as_float((uint32_t)(en >> 32));
+        uint32_t x = ok ? (a.csc ? a.fMT.div(el) : el - segbase) : 0u;
+        uint32_t iin = x;
+        io[u] = 0xffffffffu;
+        if (NQ == 2) {
+          uint32_t h = a.flo.div(x);
+          uint32_t l = x - h * a.flo.d;
+          iin = a.inner_is_lo ? l : h;
+          io[u] = ok ? (a.inner_is_lo ? h : l) : 0xffffffffu;
         }
-        cur = iout[u];
+        w[u] = Ain4[(size_t)iin * 4 + quad];
       }
-      const float v = en[u].v;
 #pragma unroll
-      for (int q = 0; q < RI / 4; ++q) {
-        t[4 * q + 0] = fmaf(v, w[u][q].x, t[4 * q + 0]);
-        t[4 * q + 1] = fmaf(v, w[u][q].y, t[4 * q + 1]);
-        t[4 * q + 2] = fmaf(v, w[u][q].z, t[4 * q + 2]);
-        t[4 * q + 3] = fmaf(v, w[u][q].w, t[4 * q + 3]);
+      for (int u = 0; u < U; ++u) {
+        if (NQ == 2 && io[u] != 0xffffffffu && io[u] != cur) {
+          if (cur != 0xffffffffu) {
+#pragma unroll
+            for (int o4 = 0; o4 < RO / 4; ++o4) {
+              const float4 wo = Aout4[(size_t)cur * 4 + o4];
+              const float wv[4] = {wo.x, wo.y, wo.z, wo.w};
+#pragma unroll
+              for (int oo = 0; oo < 4; ++oo) {
+                float* so = s + (o4 * 4 + oo) * 4;
+                so[0] = fmaf(wv[oo], t.x, so[0]);
+                so[1] = fmaf(wv[oo], t.y, so[1]);
+                so[2] = fmaf(wv[oo], t.z, so[2]);
+                so[3] = fmaf(wv[oo], t.w, so[3]);
+              }
+            }
+            t = make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+          cur = io[u];
+        }
+        t.x = fmaf(v[u], w[u].x, t.x);
+        t.y = fmaf(v[u], w[u].y, t.y);
+        t.z = fmaf(v[u], w[u].z, t.z);
+        t.w = fmaf(v[u], w[u].w, t.w);
       }
     }
   }
   if (NQ == 2) {
     if (cur != 0xffffffffu) {
-      const float* ao = a.Aout + (size_t)cur * 16;
 #pragma unroll
-      for (int o = 0; o < RO; ++o) {
-        float w = ao[o];
+      for (int o4 = 0; o4 < RO / 4; ++o4) {
+        const float4 wo = Aout4[(size_t)cur * 4 + o4];
+        const float wv[4] = {wo.x, wo.y, wo.z, wo.w};
 #pragma unroll
-        for (int j = 0; j < RI; ++j) s[o * RI + j] = fmaf(w, t[j], s[o * RI + j]);
+        for (int oo = 0; oo < 4; ++oo) {
+          float* so = s + (o4 * 4 + oo) * 4;
+          so[0] = fmaf(wv[oo], t.x, so[0]);
+          so[1] = fmaf(wv[oo], t.y, so[1]);
+          so[2] = fmaf(wv[oo], t.z, so[2]);
+          so[3] = fmaf(wv[oo], t.w, so[3]);
+        }
       }
     }
   } else {
-#pragma unroll
-    for (int j = 0; j < RI; ++j) s[j] = t[j];
+    s[0] = t.x;
+    s[1] = t.y;
+    s[2] = t.z;
+    s[3] = t.w;
   }
-  // Sum the G lanes of the segment (fixed butterfly order).
-  for (int m = 1; m < G; m <<= 1) {
+  // Sum the S slots of the segment (fixed butterfly order).
+  for (int m = LPE; m < G; m <<= 1) {
 #pragma unroll
     for (int j = 0; j < NS; ++j) s[j] += __shfl_xor(s[j], m, 64);
   }
-  if (!valid) return;
+  if (!valid || slot != 0) return;
   float* o = a.out + (size_t)seg * a.K;
 #pragma unroll
   for (int u = 0; u < NS; ++u) {
-    if ((u & (G - 1)) != gl) continue;
-    uint32_t jo = (NQ == 2) ? (uint32_t)(u / RI) : 0u, ji = (uint32_t)(u % RI);
+    const uint32_t jo = (NQ == 2) ? (uint32_t)(u / 4) : 0u;
+    const uint32_t ji = (uint32_t)(quad * 4 + (u & 3));
     if (ji >= a.Rin || jo >= (NQ == 2 ? a.Rout : 1u)) continue;
-    uint32_t kappa = (NQ == 2) ? (a.inner_is_lo ? jo * a.Rin + ji : ji * a.Rout + jo) : ji;
+    const uint32_t kappa = (NQ == 2) ? (a.inner_is_lo ? jo * a.Rin + ji : ji * a.Rout + jo) : ji;
     o[kappa] = s[u];
   }
 }
@@ -180,21 +224,29 @@ hipError_t go_ro(const SpcArgs& a, hipStream_t st) {
   }
 }
 
+// Inner rank padded to 4, 8 or 16 (the lanes of one entry must be a power
+// of two; factor rows are zero-padded to 16 columns, so 12 reads as 16).
+inline int pad_inner(uint32_t r) { return r <= 4 ? 4 : r <= 8 ? 8 : 16; }
+
 template <int NQ>
-hipError_t go_ri(const SpcArgs& a, hipStream_t st) {
-  switch (pad4(a.Rin)) {
+hipError_t go_ri(SpcArgs a, hipStream_t st) {
+  const int ri = pad_inner(a.Rin);
+  a.G *= ri / 4;
+  switch (ri) {
     case 4: return go_ro<NQ, 4>(a, st);
     case 8: return go_ro<NQ, 8>(a, st);
-    case 12: return go_ro<NQ, 12>(a, st);
     default: return go_ro<NQ, 16>(a, st);
   }
 }
 
-int lanes_per_segment(double density, uint32_t dense_len) {
+// Entry slots per segment: a power of two, at most 16, with an expected
+// eight entries or more per slot.  The lanes per segment are this times the
+// lanes per entry (at most 4), so at most 64.
+int slots_per_segment(double density, uint32_t dense_len) {
   double est = density * (double)dense_len;
-  int G = 4;
-  while (G < 64 && (double)(2 * G) * 8.0 <= est) G *= 2;
-  return G;
+  int S = 1;
+  while (S < 16 && (double)(2 * S) * 8.0 <= est) S *= 2;
+  return S;
 }
 
 // out[(o*R + r)*Q + q] = sum_i A[i*16 + r] * in[(o*I + i)*Q + q].  A
@@ -271,7 +323,7 @@ hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const
   }
   a.out = (float*)(ws + SL.TH);
   a.K = SL.KT;
-  a.G = lanes_per_segment(density, si.MT);
+  a.G = slots_per_segment(density, si.MT);
   a.hdr = sp.hdr;
   a.st_solver = (const int32_t*)(ws + SL.status);
   return q == 2 ? go_ri<2>(a, st) : go_ri<1>(a, st);
@@ -299,12 +351,12 @@ hipError_t launch_contract_head(const ShapeInfo& si, const SparsePtrs& sp, const
     a.flo = make_fastdiv(1);
     a.Ain = (const float*)(ws + SL.af[0]);
     a.Rin = ranks[0];
-    a.Aout = a.Ain;
+      a.Aout = a.Ain;
     a.Rout = 1;
   }
   a.out = (float*)(ws + SL.TT);
   a.K = SL.KH;
-  a.G = lanes_per_segment(density, si.MH);
+  a.G = slots_per_segment(density, si.MH);
   a.hdr = sp.hdr;
   a.st_solver = (const int32_t*)(ws + SL.status);
   return q == 2 ? go_ri<2>(a, st) : go_ri<1>(a, st);
