@@ -48,7 +48,7 @@ constexpr uint32_t kStage = 4096;
 // columns 4*quad .. 4*quad+3, so the LPE lanes gather one contiguous 16*LPE
 // byte factor row together (one cache line per entry instead of one per
 // lane and float4).  The G lanes of a segment form S = G / LPE entry slots.
-template <int NQ, int RI, int RO>
+template <int NQ, int RI, int RO, int CSC>
 __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
   if (a.hdr->status != 0 || *a.st_solver != 0) return;
   constexpr int LPE = RI / 4;
@@ -89,12 +89,29 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
   for (int j = 0; j < NS; ++j) s[j] = 0.f;
   uint32_t cur = 0xffffffffu;
   const uint32_t segbase = seg * a.MT;
+  // The next chunk is fetched into registers (all kPer loads issued back to
+  // back) while the current one is processed.
+  constexpr int kPer = kStage / 256;
+  const uint64_t* ent64 = reinterpret_cast<const uint64_t*>(a.ent);
+  uint64_t nxt[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t e = wg_lo + threadIdx.x + k * 256;
+    nxt[k] = e < wg_hi ? __builtin_nontemporal_load(ent64 + e) : 0ull;
+  }
   for (uint32_t c0 = wg_lo; c0 < wg_hi; c0 += kStage) {
     const uint32_t c1 = min(wg_hi, c0 + kStage);
     __syncthreads();
-    for (uint32_t e = c0 + threadIdx.x; e < c1; e += 256)
-      stage[e - c0] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(a.ent) + e);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) stage[threadIdx.x + k * 256] = nxt[k];
     __syncthreads();
+    if (c1 < wg_hi) {
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t e = c1 + threadIdx.x + k * 256;
+        nxt[k] = e < wg_hi ? __builtin_nontemporal_load(ent64 + e) : 0ull;
+      }
+    }
     uint32_t e_begin, e_step;
     if (NQ == 2) {
       e_begin = max(lo, c0);
@@ -105,8 +122,9 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
       e_step = S;
     }
     const uint32_t e_end = NQ == 2 ? min(hi, c1) : min(b1, c1);
-    // U entries per step: their factor rows are all requested before any is used.
-    constexpr int U = 2;
+    // U entries per step, straight-line code: all U factor rows are requested
+    // before any is used (an entry past the end re-reads entry e, weight 0).
+    constexpr int U = NQ == 2 ? 4 : 8;
     for (uint32_t e = e_begin; e < e_end; e += U * e_step) {
       float4 w[U];
       float v[U];
@@ -115,10 +133,10 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
       for (int u = 0; u < U; ++u) {
         const uint32_t eu = e + u * e_step;
         const bool ok = eu < e_end;
-        const uint64_t en = ok ? stage[eu - c0] : 0ull;
+        const uint64_t en = stage[(ok ? eu : e) - c0];
         const uint32_t el = (uint32_t)en;
-        v[u] = __uint_as_float((uint32_t)(en >> 32));
-        uint32_t x = ok ? (a.csc ? a.fMT.div(el) : el - segbase) : 0u;
+        v[u] = ok ? __uint_as_float((uint32_t)(en >> 32)) : 0.f;
+        const uint32_t x = CSC ? a.fMT.div(el) : el - segbase;
         uint32_t iin = x;
         io[u] = 0xffffffffu;
         if (NQ == 2) {
@@ -198,16 +216,21 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
 
 inline int pad4(uint32_t r) { return r <= 4 ? 4 : r <= 8 ? 8 : r <= 12 ? 12 : 16; }
 
-template <int NQ, int RI, int RO>
-hipError_t go(const SpcArgs& a, hipStream_t st) {
+template <int NQ, int RI, int RO, int CSC>
+hipError_t go_c(const SpcArgs& a, hipStream_t st) {
   uint32_t per = 256u / a.G;
   dim3 grid((a.nseg + per - 1) / per);
   hipEvent_t e0, e1;
-  if (timing_events(a.csc, &e0, &e1))
-    hipExtLaunchKernelGGL((k_spc<NQ, RI, RO>), grid, dim3(256), 0, st, e0, e1, 0, a);
+  if (timing_events(CSC, &e0, &e1))
+    hipExtLaunchKernelGGL((k_spc<NQ, RI, RO, CSC>), grid, dim3(256), 0, st, e0, e1, 0, a);
   else
-    hipLaunchKernelGGL((k_spc<NQ, RI, RO>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_spc<NQ, RI, RO, CSC>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
+}
+
+template <int NQ, int RI, int RO>
+hipError_t go(const SpcArgs& a, hipStream_t st) {
+  return a.csc ? go_c<NQ, RI, RO, 1>(a, st) : go_c<NQ, RI, RO, 0>(a, st);
 }
 
 template <int NQ, int RI>
