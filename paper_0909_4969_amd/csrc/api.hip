@@ -296,6 +296,11 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   S.small = take(64 * 64 * 8);
   S.lamH = take(64 * 8);
   S.part = take(64 * 64 * 64 * 8);
+  size_t skmax = 1;
+  for (int k = 0; k < d; ++k)
+    for (uint32_t side : {S.mp[k].s, S.hosvd_s[k]})
+      if (side >= 512) skmax = std::max(skmax, (size_t)((side + kSplitK - 1) / kSplitK) * side * 64);
+  S.skpart = take(skmax * 8);
   S.pv = take(1024 * 16 * 8);
   S.pi = take(1024 * 16 * 4);
   S.total = o;

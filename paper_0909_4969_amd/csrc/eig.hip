@@ -82,7 +82,8 @@ __device__ void block_sum2(double& a, double& b, double (*red)[4]) {
 }
 
 struct JacArgs {
-  const double* G;     // n x n symmetric
+  const double* G;     // n x n symmetric, as the sum of nchunk partials (n x n each)
+  uint32_t nchunk;
   uint32_t n;
   double* V;           // in: warm start if *tag == tagval; out: eigenvectors (columns, sorted)
   double* lam;         // out: eigenvalues, descending
@@ -306,9 +307,13 @@ __global__ __launch_bounds__(NT) void k_jacobi_small(JacArgs a) {
   __shared__ JacLds<NP> L;
   const int n = (int)a.n, tid = threadIdx.x;
   const bool warm = (*a.tag == a.tagval);
+  const uint32_t n2 = a.n * a.n;
   for (int e = tid; e < NP * NP; e += NT) {
     int x = e / NP, y = e % NP;
-    L.A[x][y] = (x < n && y < n) ? a.G[x * n + y] : 0.0;
+    double g = 0.0;
+    if (x < n && y < n)
+      for (uint32_t c = 0; c < a.nchunk; ++c) g += a.G[(size_t)c * n2 + x * n + y];
+    L.A[x][y] = g;
   }
   __syncthreads();
   jacobi_setup<NP, NT>(L, n, warm, a.V);
@@ -646,93 +651,137 @@ __global__ void k_small_reduce(const double* __restrict__ part, uint32_t nchunk,
   out[e] = acc;
 }
 
-// X[M x n] <- X L^{-T} where L L^T = S + shift*tr(S)/n I (S: n x n Gram of X).
-// Every workgroup factors S itself; one wave per row solves the triangle.
-__global__ __launch_bounds__(256) void k_cholqr_apply(double* __restrict__ X, uint32_t ldx, uint32_t M,
-                                                      uint32_t n, const double* __restrict__ S,
-                                                      double shift, Status s) {
+// C[M x N] partials of A[M x K] * B[K x N] (row-major, N <= 64) for long K:
+// workgroup (x, y) owns rows 64x..64x+63 and the summation slice
+// [y * kSplitK, (y + 1) * kSplitK); P[y][m][0..63] (columns >= N are 0).
+// Tiles of 32 summation indices are staged in LDS (A transposed); each
+// thread accumulates a 4 x 4 block in float64.
+__global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ A, uint32_t lda,
+                                                     const double* __restrict__ B, uint32_t ldb,
+                                                     double* __restrict__ P, uint32_t M, uint32_t K,
+                                                     uint32_t N, Status s) {
   if (s.skip()) return;
-  __shared__ double L[64][65];
-  __shared__ double trs;
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    int x = e >> 6, y = e & 63;
-    L[x][y] = (x < (int)n && y < (int)n) ? S[x * n + y] : (x == y ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (uint32_t i = 0; i < n; ++i) t += L[i][i];
-    trs = t;
-  }
-  __syncthreads();
-  if (threadIdx.x < n) L[threadIdx.x][threadIdx.x] += shift * trs / n;
-  __syncthreads();
-  for (uint32_t j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double d = L[j][j];
-      L[j][j] = d > 1e-300 ? sqrt(d) : 1.0;
+  __shared__ double As[32][68];
+  __shared__ double Bs[32][68];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const uint32_t m0 = blockIdx.x * 64, k0 = blockIdx.y * kSplitK, k1 = min(K, k0 + kSplitK);
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (uint32_t kc = k0; kc < k1; kc += 32) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid + 256 * t, r = e >> 5, kk = e & 31;
+      const uint32_t m = m0 + r, k = kc + kk;
+      va[t] = (m < M && k < k1) ? A[(size_t)m * lda + k] : 0.0;
+      const int kb = e >> 6, cb = e & 63;
+      const uint32_t k2 = kc + kb;
+      vb[t] = (k2 < k1 && (uint32_t)cb < N) ? B[(size_t)k2 * ldb + cb] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid + 256 * t;
+      As[e & 31][e >> 5] = va[t];
+      Bs[e >> 6][e & 63] = vb[t];
     }
     __syncthreads();
-    for (uint32_t i = j + 1 + threadIdx.x; i < n; i += 256) L[i][j] /= L[j][j];
-    __syncthreads();
-    for (uint32_t e = threadIdx.x; e < n * n; e += 256) {
-      uint32_t i = e / n, k = e % n;
-      if (i > j && k > j && k <= i) L[i][k] -= L[i][j] * L[k][j];
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[kk][ty * 4 + i];
+        b[i] = Bs[kk][tx * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (uint32_t m = blockIdx.x * 4 + wv; m < M; m += gridDim.x * 4) {
-    double z = lane < (int)n ? X[(size_t)m * ldx + lane] : 0.0;
-    double x = 0.0;
-    for (uint32_t j = 0; j < n; ++j) {
-      double xj = __shfl(z, j, 64) / L[j][j];
-      if (lane == (int)j) x = xj;
-      if (lane > (int)j && lane < (int)n) z -= xj * L[lane][j];
-    }
-    if (lane < (int)n) X[(size_t)m * ldx + lane] = x;
+  double* o = P + ((size_t)blockIdx.y * M + m0) * 64;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t r = ty * 4 + i;
+    if (m0 + r < M)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) o[(size_t)r * 64 + tx * 4 + j] = acc[i][j];
   }
 }
 
-// B = L^{-T} for the Cholesky factor L of S + shift * tr(S) / n * I
-// (n <= 64), so that X B has orthonormal columns when S = X^T X.  One
-// wave: lane x owns row x during the factorisation and column x of L^{-1}
-// during the forward substitution.
-__global__ __launch_bounds__(64) void k_chol_inv(const double* __restrict__ S, uint32_t n, double shift,
-                                                 double* __restrict__ B, Status s) {
+// C[m][n] = sum over the nks slices of P[slice][m][n] (fixed order), n < 64.
+__global__ void k_splitk_reduce(const double* __restrict__ P, uint32_t nks, uint32_t M,
+                                double* __restrict__ C, uint32_t ldc, Status s) {
   if (s.skip()) return;
+  const uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * 64) return;
+  double acc = 0.0;
+  for (uint32_t k = 0; k < nks; ++k) acc += P[(size_t)k * M * 64 + e];
+  C[(size_t)(e >> 6) * ldc + (e & 63)] = acc;
+}
+
+// B = L^{-T} for the Cholesky factor L of S + shift * tr(S) / n * I, with S
+// the sum of nchunk partials (n x n each, fixed order), n <= 64, so that
+// X B has orthonormal columns when S = X^T X.  One wave.  The elimination
+// runs on the unscaled Schur complements (A[x][k] -= A[x][j] A[k][j] /
+// A[j][j]), so L[x][j] = A[x][j] / sqrt(A[j][j]) afterwards; lane x owns row
+// x during the elimination and column x of L^{-1} during the substitution.
+__global__ __launch_bounds__(64) void k_chol_inv(const double* __restrict__ part, uint32_t nchunk,
+                                                 uint32_t n, double shift, double* __restrict__ B,
+                                                 Status s) {
+  if (s.skip()) return;
+  __shared__ double A[64][65];
   __shared__ double Lm[64][65];
   __shared__ double Li[64][65];
+  __shared__ double cj[64];
   const int x = threadIdx.x;
-  double tr = 0.0;
-  for (uint32_t i = 0; i < n; ++i) tr += S[i * n + i];
-  for (uint32_t j = 0; j < 64; ++j) Lm[x][j] = (x < (int)n && j < n) ? S[x * n + j] : 0.0;
-  if (x < (int)n) Lm[x][x] += shift * tr / n;
-  __builtin_amdgcn_wave_barrier();
-  for (uint32_t j = 0; j < n; ++j) {
-    if (x == (int)j) Lm[j][j] = Lm[j][j] > 1e-300 ? sqrt(Lm[j][j]) : 1.0;
-    __builtin_amdgcn_wave_barrier();
-    double d = Lm[j][j];
-    if (x > (int)j && x < (int)n) Lm[x][j] /= d;
-    __builtin_amdgcn_wave_barrier();
-    if (x > (int)j && x < (int)n) {
-      double lxj = Lm[x][j];
-      for (uint32_t k = j + 1; k <= (uint32_t)x; ++k) Lm[x][k] -= lxj * Lm[k][j];
-    }
-    __builtin_amdgcn_wave_barrier();
+  const int nn = (int)n;
+  const uint32_t n2 = n * n;
+  for (int y = 0; y < 64; ++y) {
+    double v = 0.0;
+    if (x < nn && y < nn)
+      for (uint32_t c = 0; c < nchunk; ++c) v += part[(size_t)c * n2 + x * n + y];
+    else if (x == y)
+      v = 1.0;
+    A[x][y] = v;
   }
-  for (uint32_t i = 0; i < 64; ++i) Li[i][x] = 0.0;
-  __builtin_amdgcn_wave_barrier();
-  if (x < (int)n)
-    for (uint32_t i = x; i < n; ++i) {
-      double v = (i == (uint32_t)x) ? 1.0 : 0.0;
-      for (uint32_t k = x; k < i; ++k) v -= Lm[i][k] * Li[k][x];
+  double tr = x < nn ? A[x][x] : 0.0;
+  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+  if (x < nn) A[x][x] += shift * tr / n;
+  __syncthreads();
+  for (int j = 0; j < nn; ++j) {
+    const double dj = A[j][j];
+    const double piv = dj > 1e-300 ? dj : 1.0;
+    cj[x] = A[x][j] / piv;
+    __syncthreads();
+    if (x > j && x < nn) {
+      const double axj = A[x][j];
+      for (int k = j + 1; k <= x; ++k) A[x][k] -= axj * cj[k];
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < 64; ++k) {
+    const double dk = A[k][k];
+    const double r = dk > 1e-300 ? sqrt(dk) : 1.0;
+    Lm[x][k] = (k <= x && x < nn && k < nn) ? (k == x ? r : A[x][k] / r) : (x == k ? 1.0 : 0.0);
+    Li[x][k] = 0.0;
+  }
+  __syncthreads();
+  for (int i = 0; i < nn; ++i) {
+    if (x <= i) {
+      double v = (i == x) ? 1.0 : 0.0;
+      for (int k = x; k < i; ++k) v -= Lm[i][k] * Li[k][x];
       Li[i][x] = v / Lm[i][i];
     }
-  __builtin_amdgcn_wave_barrier();
+    __syncthreads();
+  }
   // B[k][j] = Li[j][k]
-  if (x < (int)n)
-    for (uint32_t j = 0; j < n; ++j) B[x * n + j] = Li[j][x];
+  if (x < nn)
+    for (int j = 0; j < nn; ++j) B[x * n + j] = Li[j][x];
 }
 
 // Deterministic start block for the subspace iteration (hash of position).
@@ -1051,34 +1100,33 @@ __global__ void k_set_int(int32_t* p, int32_t v) {
   if (threadIdx.x == 0) *p = v;
 }
 
-void cholqr2(const Ctx& c, double* X, uint32_t ldx, uint32_t M, uint32_t n, bool with_done) {
-  Status s = c.stat(with_done);
-  uint32_t nchunk = cdiv(M, 256);
-  if (nchunk > 64) nchunk = 64;
-  if (nchunk < 1) nchunk = 1;
-  uint32_t rows = cdiv(M, nchunk);
-  for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, X, ldx, X, ldx, M, n, rows,
-                       c.d(c.SL->part), s);
-    hipLaunchKernelGGL(k_small_reduce, dim3(cdiv(n * n, 256)), dim3(256), 0, c.st, c.d(c.SL->part),
-                       nchunk, n * n, c.d(c.SL->small), s);
-    uint32_t g = cdiv(M, 4);
-    if (g > 128) g = 128;
-    hipLaunchKernelGGL(k_cholqr_apply, dim3(g), dim3(256), 0, c.st, X, ldx, M, n, c.d(c.SL->small),
-                       pass == 0 ? 1e-15 : 0.0, s);
-  }
-}
-
 void gemm(const Ctx& c, const double* A, uint32_t lda, const double* B, uint32_t ldb, double* C,
           uint32_t ldc, uint32_t M, uint32_t K, uint32_t N, bool with_done) {
   hipLaunchKernelGGL(k_gemm64, dim3(cdiv(M, 16)), dim3(256), 0, c.st, A, lda, B, ldb, C, ldc, M, K,
                      N, c.stat(with_done));
 }
 
-void jacobi(const Ctx& c, const double* G, uint32_t n, double* V, double* lam, int32_t* tag,
-            int32_t tagval, bool with_done, int rtop, double tol2 = kOffTol2) {
+// C (s x 64, ld kBlock) = G (s x s) * X (s x n, ld kBlock): split over the
+// summation index when it is long, so that every CU gets a tile.
+void gemm_sq(const Ctx& c, const double* G, uint32_t s, const double* X, double* C, uint32_t n,
+             bool with_done) {
+  if (s < 512) {
+    gemm(c, G, s, X, kBlock, C, kBlock, s, s, n, with_done);
+    return;
+  }
+  const uint32_t nks = cdiv(s, kSplitK);
+  double* P = c.d(c.SL->skpart);
+  hipLaunchKernelGGL(k_gemm_splitk, dim3(cdiv(s, 64), nks), dim3(256), 0, c.st, G, s, X, kBlock, P, s,
+                     s, n, c.stat(with_done));
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv((uint64_t)s * 64, 256)), dim3(256), 0, c.st, P, nks, s,
+                     C, kBlock, c.stat(with_done));
+}
+
+void jacobi(const Ctx& c, const double* G, uint32_t nchunk, uint32_t n, double* V, double* lam,
+            int32_t* tag, int32_t tagval, bool with_done, int rtop, double tol2 = kOffTol2) {
   JacArgs a;
   a.G = G;
+  a.nchunk = nchunk;
   a.n = n;
   a.V = V;
   a.lam = lam;
@@ -1095,38 +1143,40 @@ void jacobi(const Ctx& c, const double* G, uint32_t n, double* V, double* lam, i
     hipLaunchKernelGGL((k_jacobi_small<64, 1024>), dim3(1), dim3(1024), 0, c.st, a);
 }
 
-// X (M x n, ld kBlock) <- X with orthonormal columns, by two Cholesky-QR
-// passes (the first shifted by 1e-15 tr(S) / n); Y is scratch of X's size.
-void orthonormalise(const Ctx& c, double* X, double* Y, uint32_t M, uint32_t n, bool with_done) {
+// Cholesky-QR of X (M x n, ld kBlock): `passes` passes (the first shifted
+// by 1e-15 tr(S) / n), alternating between X and the scratch Y.  Returns
+// the buffer holding the result (X after an even number of passes).
+double* orthonormalise(const Ctx& c, double* X, double* Y, uint32_t M, uint32_t n, int passes,
+                       bool with_done) {
   Status sd = c.stat(with_done);
   uint32_t nchunk = cdiv(M, 256);
   if (nchunk > 64) nchunk = 64;
   uint32_t rows = cdiv(M, nchunk);
-  double* S = c.d(c.SL->small);
   double* B = c.d(c.SL->H);
   double* src = X;
   double* dst = Y;
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, src, kBlock, src, kBlock, M, n,
                        rows, c.d(c.SL->part), sd);
-    hipLaunchKernelGGL(k_small_reduce, dim3(cdiv(n * n, 256)), dim3(256), 0, c.st, c.d(c.SL->part),
-                       nchunk, n * n, S, sd);
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, c.st, S, n, pass == 0 ? 1e-15 : 0.0, B, sd);
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, c.st, c.d(c.SL->part), nchunk, n,
+                       pass == 0 ? 1e-15 : 0.0, B, sd);
     gemm(c, src, kBlock, B, n, dst, kBlock, M, n, n, with_done);
     double* t = src;
     src = dst;
     dst = t;
   }
-  // after two passes the result is back in X
+  return src;
 }
 
 // Top eigenpairs of the s x s matrix G (s > 64) by block subspace iteration
-// on b = min(64, max(32, 2R rounded up to 16)) columns: two multiplications
-// by G per orthonormalisation, Rayleigh-Ritz every 8 steps and at the end,
-// stopping once the top R Ritz residuals are below 1e-10 of the largest
-// Ritz value.  Q (s x 64, ld 64) holds the block (warm start if *tag ==
-// tagval); on return its first R columns are the Ritz vectors and lam the
-// Ritz values, descending.
+// on b = min(64, max(32, 2R rounded up to 16)) columns: the block is
+// multiplied by G every step and re-orthonormalised (one Cholesky-QR pass)
+// after every second step; every 8 steps and at the end, Rayleigh-Ritz on
+// the orthonormalised block (Jacobi on b x b), and the iteration stops once
+// the top R Ritz residuals are below 1e-10 of the largest Ritz value (the
+// remaining steps are skipped on the device).  Q (s x 64, ld 64) holds the
+// start block (warm start if *tag == tagval); on return its first R columns
+// are the Ritz vectors and lam the Ritz values, descending.
 void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double* Q, double* lam,
                    int32_t* tag, int32_t tagval, int maxit, int32_t* stat_it) {
   uint32_t b = 2 * R;
@@ -1138,41 +1188,51 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagRR, 0);
   hipLaunchKernelGGL(k_ss_init, dim3(cdiv((uint64_t)s * b, 256)), dim3(256), 0, c.st, Q, kBlock, s,
                      b, tag, tagval, c.stat());
-  double* Z = c.d(c.SL->Zs);
-  double* Z2 = c.d(c.SL->Z2s);
+  // Buffers: the Ritz vectors of every Rayleigh-Ritz step go to Qr (so the
+  // converged ones stay there when later steps are skipped); the block and
+  // its products rotate through Q, Z and Z2.
   double* Qr = c.d(c.SL->Qrs);
-  double* H = c.d(c.SL->H);
+  double* H = c.d(c.SL->part);
   double* VH = c.d(c.SL->VH);
   double* lamH = c.d(c.SL->lamH);
-  orthonormalise(c, Q, Z, s, b, false);
+  double* pool[3] = {Q, c.d(c.SL->Zs), c.d(c.SL->Z2s)};
+  auto other = [&](const double* a, const double* b2) {
+    for (double* p : pool)
+      if (p != a && p != b2) return p;
+    return pool[0];
+  };
+  double* cur = orthonormalise(c, Q, other(Q, nullptr), s, b, 2, false);
   Status sd = c.stat(true);
-  const uint32_t nb = cdiv((uint64_t)s * kBlock, 256);
   for (int it = 0; it < maxit; ++it) {
     const bool last = it == maxit - 1;
     const bool rr = (it % 8 == 7) || last;
-    gemm(c, G, s, Q, kBlock, Z, kBlock, s, s, b, true);
-    if (it % 2 == 1 || rr) {
-      orthonormalise(c, Z, Z2, s, b, true);
+    double* z = other(cur, nullptr);
+    gemm_sq(c, G, s, cur, z, b, true);
+    if (!rr) {
+      if (it % 2 == 1) z = orthonormalise(c, z, other(z, nullptr), s, b, 1, true);
+      cur = z;
+      continue;
     }
-    hipLaunchKernelGGL(k_copy64, dim3(nb), dim3(256), 0, c.st, Z, Q, s * kBlock, sd);
-    if (rr) {
-      gemm(c, G, s, Q, kBlock, Z, kBlock, s, s, b, true);
-      uint32_t nchunk = cdiv(s, 256);
-      if (nchunk > 64) nchunk = 64;
-      uint32_t rows = cdiv(s, nchunk);
-      hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, Q, kBlock, Z, kBlock, s, b,
-                         rows, c.d(c.SL->part), sd);
-      hipLaunchKernelGGL(k_small_reduce, dim3(cdiv(b * b, 256)), dim3(256), 0, c.st, c.d(c.SL->part),
-                         nchunk, b * b, H, sd);
-      jacobi(c, H, b, VH, lamH, tags + kTagRR, 0x52520000 | (int32_t)b, true, (int)R, 1e-28);
-      gemm(c, Q, kBlock, VH, b, Qr, kBlock, s, b, b, true);
-      gemm(c, Z, kBlock, VH, b, Z2, kBlock, s, b, b, true);
-      hipLaunchKernelGGL(k_copy64, dim3(nb), dim3(256), 0, c.st, Qr, Q, s * kBlock, sd);
-      hipLaunchKernelGGL(k_copy64, dim3(1), dim3(256), 0, c.st, lamH, lam, b, sd);
-      hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, Z2, Qr, kBlock, s, lamH, R, 1e-10,
-                         tags + kTagDone, last ? 1 : 0, stat_it, it, c.stat(true));
-    }
+    double* w = other(z, nullptr);
+    z = orthonormalise(c, z, w, s, b, 2, true);   // result back in z
+    w = other(z, nullptr);
+    gemm_sq(c, G, s, z, w, b, true);               // w = G z
+    uint32_t nchunk = cdiv(s, 256);
+    if (nchunk > 64) nchunk = 64;
+    uint32_t rows = cdiv(s, nchunk);
+    hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, z, kBlock, w, kBlock, s, b, rows,
+                       H, sd);
+    jacobi(c, H, nchunk, b, VH, lamH, tags + kTagRR, 0x52520000 | (int32_t)b, true, (int)R, 1e-28);
+    double* zr = other(z, w);
+    gemm(c, z, kBlock, VH, b, Qr, kBlock, s, b, b, true);
+    gemm(c, w, kBlock, VH, b, zr, kBlock, s, b, b, true);
+    hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, zr, Qr, kBlock, s, lamH, R, 1e-10,
+                       tags + kTagDone, last ? 1 : 0, stat_it, it, c.stat(true));
+    cur = Qr;
   }
+  hipLaunchKernelGGL(k_copy64, dim3(cdiv((uint64_t)s * kBlock, 256)), dim3(256), 0, c.st, Qr, Q,
+                     s * kBlock, c.stat());
+  hipLaunchKernelGGL(k_copy64, dim3(1), dim3(256), 0, c.st, lamH, lam, b, c.stat());
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tag, tagval);
 }
 
@@ -1277,18 +1337,10 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
   hipError_t e = launch_gram_y(SL, ws, k, hdr, st);
   if (e != hipSuccess) return e;
   const double* G = c.d(SL.G);
-  double* V;
-  uint32_t ldv;
-  if (m.s <= (uint32_t)kSmallEig) {
-    V = c.d(m.V);
-    ldv = m.s;
-    jacobi(c, G, m.s, V, c.d(m.lam), c.tags() + k, tagval, false, (int)m.R);
-  } else {
-    V = c.d(m.Q64);
-    ldv = kBlock;
-    subspace_topk(c, G, m.s, m.R, V, c.d(m.lam), c.tags() + k, tagval, 24,
-                  (int32_t*)(ws + SL.status + 96) + k);
-  }
+  double* V = c.d(m.Q64);
+  const uint32_t ldv = kBlock;
+  subspace_topk(c, G, m.s, m.R, V, c.d(m.lam), c.tags() + k, tagval, 24,
+                (int32_t*)(ws + SL.status + 96) + k);
   if (m.kside) {
     uint32_t J = m.O * m.Q;
     hipLaunchKernelGGL(k_backproject_dense, dim3(cdiv(m.I, 256)), dim3(256), 0, st,
@@ -1319,7 +1371,7 @@ hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const So
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, tagc, 0);
   if (s <= (uint32_t)kSmallEig) {
     ldv = s;
-    jacobi(c, G, s, V, lam, tagc, 0x48000000 | (int32_t)s, false, R);
+    jacobi(c, G, 1, s, V, lam, tagc, 0x48000000 | (int32_t)s, false, R);
   } else {
     ldv = kBlock;
     subspace_topk(c, G, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 96,

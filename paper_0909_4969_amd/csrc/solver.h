@@ -37,6 +37,7 @@ struct ModePlan {
 };
 
 constexpr uint32_t kBlock = 64;          // subspace block for sides > kSmallEig
+constexpr uint32_t kSplitK = 256;        // summation slice of the split products by G
 
 // Status region: int32 status word at +0, int32 tags[16] at +16 (eigen
 // warm-start tags of modes 0..7, then kTagRR, kTagCold, kTagDone), int32
@@ -55,6 +56,7 @@ struct SolverLayout {
   size_t Zs, Z2s, Qrs, Qhs;              // float64 zrows x 64 each
   size_t H, VH, lamH, small;             // float64 64 x 64 (lamH: 64)
   size_t part;                           // float64 64 x 64 x 64 partials
+  size_t skpart;                         // float64 split-K partials of G * block
   size_t pv, pi;                         // column-max partials (1024 x 16)
   size_t total;
   ModePlan mp[kMaxD];
