@@ -284,6 +284,8 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   S.Gpart_elems = std::max<size_t>(std::max<size_t>(64 * (size_t)smax_sweep * smax_sweep,
                                                     16 * (size_t)hs_iside_max * hs_iside_max),
                                    65536);
+  // MFMA row-side Grams keep up to 1024 block partials of at most 64 x 64
+  if (hs_iside_max > 1) S.Gpart_elems = std::max<size_t>(S.Gpart_elems, 1024 * 64 * 64);
   S.Gpart = take(S.Gpart_elems * 8);
   S.Aw = take((size_t)imax * 16 * 8);
   S.zrows = zrows;

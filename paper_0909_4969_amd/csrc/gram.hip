@@ -13,6 +13,8 @@
 // Products are float32, summed in float32 over 32 terms and then in
 // float64; each workgroup owns a 64x64 tile and a slice of the summation
 // range, and the slices are added in a fixed order.
+#include <algorithm>
+
 #include "solver.h"
 
 namespace mach {
@@ -212,7 +214,181 @@ __global__ __launch_bounds__(256) void k_gram_rows_sparse(const Entry* __restric
     for (uint32_t j = lane; j < MH; j += 64) G[(size_t)r * MH + j] = row[j];
 }
 
+// ---------------------------------------------------------------------------
+// Row-side Gram of the sampled unfolding on MFMA (float32 products, float32
+// accumulation over one chunk of columns, then float64).  Applies when the
+// unfolding's rows are 64-aligned runs of the linear index (Q a multiple of
+// 64), so that 64 columns of one row are one bitmap word and the kept
+// values of that word are consecutive entries of the l-ordered list.
+//
+// The I x I Gram is cut into RB x RB blocks; workgroup (blk, slice) owns
+// the upper-triangle block pair blk = (bx, by), bx <= by, and a slice of the
+// columns.  Per chunk of CW = 4096 / RB columns it expands both row blocks
+// of Xhat into LDS (dense float32, zeros where not kept), then its four
+// waves take every fourth group of 4 columns and issue
+// v_mfma_f32_16x16x4f32 on all (RB/16)^2 16x16 tiles.  The wave sums are
+// added in a fixed order and the block partial is written to
+// part[slice][blk]; a second kernel adds the slices in order and fills both
+// triangles.
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct MfmaGramArgs {
+  const uint64_t* bitmap;
+  const uint32_t* wrank;
+  const Entry* coo;
+  uint32_t I, Q, J;
+  FastDiv fQ;
+  uint32_t nb, nblk;       // row blocks, block pairs (nb (nb + 1) / 2)
+  uint32_t cps;            // chunks per slice
+  double* part;            // [slice][blk][RB][RB]
+  const SampleHdr* hdr;
+  const int32_t* st_solver;
+};
+
+template <int RB>
+__device__ __forceinline__ void mfma_stage(const MfmaGramArgs& a, uint32_t row0, uint32_t jc,
+                                           float (*M)[4096 / RB + 4]) {
+  constexpr int CW = 4096 / RB, WPR = CW / 64;
+  const int t = threadIdx.x, q = t & 3, rw = t >> 2;
+  const int r = rw / WPR, wd = rw % WPR;
+  const uint32_t i = row0 + r, j = jc + wd * 64;
+  uint64_t word = 0;
+  uint32_t base = 0;
+  if (i < a.I && j < a.J) {
+    const uint32_t qq = a.fQ.div(j);
+    const uint32_t l0 = qq * a.I * a.Q + (j - qq * a.Q) + i * a.Q;
+    word = a.bitmap[l0 >> 6];
+    base = a.wrank[l0 >> 6];
+  }
+#pragma unroll
+  for (int bb = 0; bb < 16; ++bb) {
+    const int bit = q * 16 + bb;
+    float v = 0.f;
+    if ((word >> bit) & 1ull) {
+      const uint64_t below = bit ? (word & ((~0ull) >> (64 - bit))) : 0ull;
+      v = a.coo[base + (uint32_t)__popcll(below)].v;
+    }
+    M[r][wd * 64 + bit] = v;
+  }
+}
+
+template <int RB>
+__global__ __launch_bounds__(256) void k_gram_mfma(MfmaGramArgs a) {
+  if (a.hdr->status != 0 || *a.st_solver != 0) return;
+  constexpr int CW = 4096 / RB, TB = RB / 16, KS = CW / 4;
+  __shared__ float Ma[RB][CW + 4];
+  __shared__ float Mb[RB][CW + 4];
+  uint32_t by = 0;
+  while ((by + 1) * (by + 2) / 2 <= blockIdx.x) ++by;
+  const uint32_t bx = blockIdx.x - by * (by + 1) / 2;
+  const bool diag = bx == by;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  v4f acc[TB][TB];
+  double dacc[TB][TB][4];
+#pragma unroll
+  for (int x = 0; x < TB; ++x)
+#pragma unroll
+    for (int y = 0; y < TB; ++y) {
+      acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dacc[x][y][v] = 0.0;
+    }
+  const uint32_t c0 = blockIdx.y * a.cps;
+  for (uint32_t c = c0; c < c0 + a.cps; ++c) {
+    const uint32_t jc = c * CW;
+    if (jc >= a.J) break;
+    __syncthreads();
+    mfma_stage<RB>(a, bx * RB, jc, Ma);
+    if (!diag) mfma_stage<RB>(a, by * RB, jc, Mb);
+    __syncthreads();
+    float (*B)[CW + 4] = diag ? Ma : Mb;
+    for (int ks = w; ks < KS; ks += 4) {
+      float av[TB], bv[TB];
+#pragma unroll
+      for (int x = 0; x < TB; ++x) {
+        av[x] = Ma[x * 16 + li][ks * 4 + lk];
+        bv[x] = B[x * 16 + li][ks * 4 + lk];
+      }
+#pragma unroll
+      for (int x = 0; x < TB; ++x)
+#pragma unroll
+        for (int y = 0; y < TB; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
+#pragma unroll
+    for (int x = 0; x < TB; ++x)
+#pragma unroll
+      for (int y = 0; y < TB; ++y) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dacc[x][y][v] += (double)acc[x][y][v];
+        acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+  }
+  // Wave sums in order 0..3 through LDS (reusing the staging buffers).
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(&Ma[0][0]);
+  static_assert(sizeof(Ma) + sizeof(Mb) >= RB * RB * sizeof(double), "reduction buffer");
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+#pragma unroll
+      for (int x = 0; x < TB; ++x)
+#pragma unroll
+        for (int y = 0; y < TB; ++y)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = x * 16 + lk * 4 + v, col = y * 16 + li;
+            double* p = red + row * RB + col;
+            *p = (ww == 0) ? dacc[x][y][v] : *p + dacc[x][y][v];
+          }
+    }
+    __syncthreads();
+  }
+  double* out = a.part + ((size_t)blockIdx.y * a.nblk + blockIdx.x) * RB * RB;
+  for (int e = threadIdx.x; e < RB * RB; e += 256) out[e] = red[e];
+}
+
+template <int RB>
+__global__ void k_gram_mfma_reduce(const double* __restrict__ part, uint32_t nslice, uint32_t nblk,
+                                   uint32_t I, double* __restrict__ G, const SampleHdr* hdr,
+                                   const int32_t* st_solver) {
+  if (hdr->status != 0 || *st_solver != 0) return;
+  const uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= I * I) return;
+  uint32_t x = e / I, y = e % I;
+  uint32_t bx = x / RB, by = y / RB, xx = x % RB, yy = y % RB;
+  if (bx > by) {
+    uint32_t t = bx; bx = by; by = t;
+    t = xx; xx = yy; yy = t;
+  }
+  const uint32_t blk = by * (by + 1) / 2 + bx;
+  double acc = 0.0;
+  for (uint32_t s = 0; s < nslice; ++s) acc += part[((size_t)s * nblk + blk) * RB * RB + xx * RB + yy];
+  G[e] = acc;
+}
+
+template <int RB>
+hipError_t gram_mfma_run(MfmaGramArgs a, double* G, size_t part_elems, hipStream_t st) {
+  constexpr uint32_t CW = 4096 / RB;
+  a.nb = (a.I + RB - 1) / RB;
+  a.nblk = a.nb * (a.nb + 1) / 2;
+  const uint32_t chunks = (a.J + CW - 1) / CW;
+  // About 16 chunks per slice, at most 1024 workgroups' partials.
+  uint32_t nslice = (chunks + 15) / 16;
+  const uint32_t cap = (uint32_t)std::min<size_t>(1024 / a.nblk, part_elems / ((size_t)a.nblk * RB * RB));
+  if (nslice > cap) nslice = cap;
+  if (nslice < 1) nslice = 1;
+  a.cps = (chunks + nslice - 1) / nslice;
+  nslice = (chunks + a.cps - 1) / a.cps;
+  hipLaunchKernelGGL((k_gram_mfma<RB>), dim3(a.nblk, nslice), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_gram_mfma_reduce<RB>), dim3((a.I * a.I + 255) / 256), dim3(256), 0, st, a.part,
+                     nslice, a.nblk, a.I, G, a.hdr, a.st_solver);
+  return hipGetLastError();
+}
+
 }  // namespace
+
 
 bool sparse_tail_gram_ok(const ShapeInfo& si, const SolverLayout& SL, int n) {
   return SL.hosvd_kside[n] && n == si.d - 1 && si.h == si.d - 1 && si.MH <= kSparseGramMaxRows;
@@ -281,6 +457,23 @@ hipError_t launch_gram_xhat(const ShapeInfo& si, const SparsePtrs& sp, const Sol
   a.part = (double*)(ws + SL.Gpart);
   a.st_solver = (const int32_t*)(ws + SL.status);
   a.hdr = sp.hdr;
+  if (!a.kside && a.Q % 64 == 0 && a.I <= kMfmaGramMaxRows) {
+    MfmaGramArgs m{};
+    m.bitmap = sp.bitmap;
+    m.wrank = sp.wrank;
+    m.coo = sp.coo_l;
+    m.I = a.I;
+    m.Q = a.Q;
+    m.J = a.J;
+    m.fQ = a.fQ;
+    m.part = a.part;
+    m.hdr = sp.hdr;
+    m.st_solver = a.st_solver;
+    double* G = (double*)(ws + SL.G);
+    if (a.I <= 16) return gram_mfma_run<16>(m, G, SL.Gpart_elems, st);
+    if (a.I <= 32) return gram_mfma_run<32>(m, G, SL.Gpart_elems, st);
+    return gram_mfma_run<64>(m, G, SL.Gpart_elems, st);
+  }
   MaskedLoad ld{sp.bitmap, sp.wrank, sp.coo_l};
   return gram_run(a, ld, (double*)(ws + SL.G), SL.Gpart_elems, st);
 }

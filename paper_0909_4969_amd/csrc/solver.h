@@ -38,6 +38,7 @@ struct ModePlan {
 
 constexpr uint32_t kBlock = 64;          // subspace block for sides > kSmallEig
 constexpr uint32_t kSplitK = 256;        // summation slice of the split products by G
+constexpr uint32_t kMfmaGramMaxRows = 1024;  // row-side HOSVD Grams on MFMA up to this side
 
 // Status region: int32 status word at +0, int32 tags[16] at +16 (eigen
 // warm-start tags of modes 0..7, then kTagRR, kTagCold, kTagDone), int32
