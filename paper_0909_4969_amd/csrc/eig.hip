@@ -82,7 +82,7 @@ __device__ void block_sum2(double& a, double& b, double (*red)[4]) {
 }
 
 struct JacArgs {
-  const double* G;     // n x n symmetric, as the sum of nchunk partials (n x n each)
+  const double* G;     // n x n symmetric: entry (x, y) = sum_c G[(x * n + y) * nchunk + c]
   uint32_t nchunk;
   uint32_t n;
   double* V;           // in: warm start if *tag == tagval; out: eigenvectors (columns, sorted)
@@ -307,12 +307,14 @@ __global__ __launch_bounds__(NT) void k_jacobi_small(JacArgs a) {
   __shared__ JacLds<NP> L;
   const int n = (int)a.n, tid = threadIdx.x;
   const bool warm = (*a.tag == a.tagval);
-  const uint32_t n2 = a.n * a.n;
   for (int e = tid; e < NP * NP; e += NT) {
     int x = e / NP, y = e % NP;
     double g = 0.0;
-    if (x < n && y < n)
-      for (uint32_t c = 0; c < a.nchunk; ++c) g += a.G[(size_t)c * n2 + x * n + y];
+    if (x < n && y < n) {
+      const double* p = a.G + (size_t)(x * n + y) * a.nchunk;
+#pragma unroll 16
+      for (uint32_t c = 0; c < a.nchunk; ++c) g += p[c];
+    }
     L.A[x][y] = g;
   }
   __syncthreads();
@@ -597,7 +599,8 @@ __global__ __launch_bounds__(256) void k_gemm64(const double* __restrict__ A, ui
   }
 }
 
-// part[chunk][x][y] = sum over the chunk's rows m of A[m][x] * B[m][y]  (x, y < n <= 64)
+// part[x][y][chunk] = sum over the chunk's rows m of A[m][x] * B[m][y]  (x, y < n <= 64;
+// chunk-minor, so that a consumer reads the partials of one entry contiguously)
 __global__ __launch_bounds__(256) void k_atb_partial(const double* __restrict__ A, uint32_t lda,
                                                      const double* __restrict__ B, uint32_t ldb,
                                                      uint32_t M, uint32_t n, uint32_t rows,
@@ -631,13 +634,12 @@ __global__ __launch_bounds__(256) void k_atb_partial(const double* __restrict__ 
     }
     __syncthreads();
   }
-  double* o = part + (size_t)blockIdx.x * n * n;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       uint32_t x = tx * 4 + i, y = ty * 4 + j;
-      if (x < n && y < n) o[x * n + y] = acc[i][j];
+      if (x < n && y < n) part[(size_t)(x * n + y) * gridDim.x + blockIdx.x] = acc[i][j];
     }
 }
 
@@ -653,8 +655,8 @@ __global__ void k_small_reduce(const double* __restrict__ part, uint32_t nchunk,
 
 // C[M x N] partials of A[M x K] * B[K x N] (row-major, N <= 64) for long K:
 // workgroup (x, y) owns rows 64x..64x+63 and the summation slice
-// [y * kSplitK, (y + 1) * kSplitK); P[y][m][0..63] (columns >= N are 0).
-// Tiles of 32 summation indices are staged in LDS (A transposed); each
+// [y * kSplitK, (y + 1) * kSplitK) (a single slice covers all of K);
+// P[y][m][0..63] (columns >= N are 0).  Tiles of 32 summation indices are staged in LDS (A transposed); each
 // thread accumulates a 4 x 4 block in float64.
 __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ A, uint32_t lda,
                                                      const double* __restrict__ B, uint32_t ldb,
@@ -664,7 +666,8 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ 
   __shared__ double As[32][68];
   __shared__ double Bs[32][68];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const uint32_t m0 = blockIdx.x * 64, k0 = blockIdx.y * kSplitK, k1 = min(K, k0 + kSplitK);
+  const uint32_t m0 = blockIdx.x * 64, k0 = blockIdx.y * kSplitK;
+  const uint32_t k1 = gridDim.y == 1 ? K : min(K, k0 + kSplitK);
   double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -725,63 +728,97 @@ __global__ void k_splitk_reduce(const double* __restrict__ P, uint32_t nks, uint
 }
 
 // B = L^{-T} for the Cholesky factor L of S + shift * tr(S) / n * I, with S
-// the sum of nchunk partials (n x n each, fixed order), n <= 64, so that
-// X B has orthonormal columns when S = X^T X.  One wave.  The elimination
-// runs on the unscaled Schur complements (A[x][k] -= A[x][j] A[k][j] /
-// A[j][j]), so L[x][j] = A[x][j] / sqrt(A[j][j]) afterwards; lane x owns row
-// x during the elimination and column x of L^{-1} during the substitution.
-__global__ __launch_bounds__(64) void k_chol_inv(const double* __restrict__ part, uint32_t nchunk,
-                                                 uint32_t n, double shift, double* __restrict__ B,
-                                                 Status s) {
+// the sum of nchunk partials (chunk-minor, fixed order), n <= 64, so that
+// X B has orthonormal columns when S = X^T X.  The elimination runs on the
+// unscaled Schur complements, A[x][k] -= A[x][j] A[k][j] / A[j][j] for
+// j < k <= x, with the column A[.][j] copied out first so that each batch of
+// trailing entries is read before any is written; afterwards L[x][j] =
+// A[x][j] / sqrt(A[j][j]).  Wave 0 then forms L^{-1} (lane x: column x) by
+// forward substitution.
+__global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ part, uint32_t nchunk,
+                                                  uint32_t n, double shift, double* __restrict__ B,
+                                                  Status s) {
   if (s.skip()) return;
   __shared__ double A[64][65];
   __shared__ double Lm[64][65];
   __shared__ double Li[64][65];
   __shared__ double cj[64];
-  const int x = threadIdx.x;
+  __shared__ double trs;
+  const int tid = threadIdx.x, x = tid & 63;
   const int nn = (int)n;
-  const uint32_t n2 = n * n;
-  for (int y = 0; y < 64; ++y) {
-    double v = 0.0;
-    if (x < nn && y < nn)
-      for (uint32_t c = 0; c < nchunk; ++c) v += part[(size_t)c * n2 + x * n + y];
-    else if (x == y)
-      v = 1.0;
-    A[x][y] = v;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    double v = (r == c) ? 1.0 : 0.0;
+    if (r < nn && c < nn) {
+      const double* p = part + (size_t)(r * n + c) * nchunk;
+      v = 0.0;
+#pragma unroll 16
+      for (uint32_t ch = 0; ch < nchunk; ++ch) v += p[ch];
+    }
+    A[r][c] = v;
   }
-  double tr = x < nn ? A[x][x] : 0.0;
-  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
-  if (x < nn) A[x][x] += shift * tr / n;
+  __syncthreads();
+  if (tid < 64) {
+    double tr = x < nn ? A[x][x] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+    if (x == 0) trs = tr;
+  }
+  __syncthreads();
+  if (tid < nn) A[tid][tid] += shift * trs / n;
   __syncthreads();
   for (int j = 0; j < nn; ++j) {
     const double dj = A[j][j];
-    const double piv = dj > 1e-300 ? dj : 1.0;
-    cj[x] = A[x][j] / piv;
+    const double ip = 1.0 / (dj > 1e-300 ? dj : 1.0);
+    if (tid < 64) cj[x] = x < nn ? A[x][j] : 0.0;
     __syncthreads();
-    if (x > j && x < nn) {
-      const double axj = A[x][j];
-      for (int k = j + 1; k <= x; ++k) A[x][k] -= axj * cj[k];
+    const int m = nn - j - 1, mm = m * m;
+    for (int base = 0; base < mm; base += 256 * 4) {
+      double val[4];
+      int xs[4], ks[4];
+      bool act[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int e = base + tid + 256 * t;
+        const bool in = e < mm;
+        const int q = in ? e / m : 0;
+        xs[t] = j + 1 + q;                      // in [j + 1, nn) whenever in
+        ks[t] = in ? j + 1 + (e - q * m) : xs[t];
+        act[t] = in && ks[t] <= xs[t];
+        val[t] = A[in ? xs[t] : 0][in ? ks[t] : 0];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (act[t]) A[xs[t]][ks[t]] = val[t] - cj[xs[t]] * cj[ks[t]] * ip;
     }
     __syncthreads();
   }
-  for (int k = 0; k < 64; ++k) {
-    const double dk = A[k][k];
-    const double r = dk > 1e-300 ? sqrt(dk) : 1.0;
-    Lm[x][k] = (k <= x && x < nn && k < nn) ? (k == x ? r : A[x][k] / r) : (x == k ? 1.0 : 0.0);
-    Li[x][k] = 0.0;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    double v = (r == c) ? 1.0 : 0.0;
+    if (r < nn && c <= r) {
+      const double dc = A[c][c];
+      const double sc = dc > 1e-300 ? sqrt(dc) : 1.0;
+      v = (c == r) ? sc : A[r][c] / sc;
+    }
+    Lm[r][c] = v;
+    Li[r][c] = 0.0;
   }
   __syncthreads();
+  if (tid >= 64) return;
   for (int i = 0; i < nn; ++i) {
     if (x <= i) {
       double v = (i == x) ? 1.0 : 0.0;
       for (int k = x; k < i; ++k) v -= Lm[i][k] * Li[k][x];
       Li[i][x] = v / Lm[i][i];
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
   }
   // B[k][j] = Li[j][k]
-  if (x < nn)
-    for (int j = 0; j < nn; ++j) B[x * n + j] = Li[j][x];
+  for (int e = x; e < nn * nn; e += 64) {
+    const int k = e / nn, j = e % nn;
+    B[e] = Li[j][k];
+  }
 }
 
 // Deterministic start block for the subspace iteration (hash of position).
@@ -1110,16 +1147,14 @@ void gemm(const Ctx& c, const double* A, uint32_t lda, const double* B, uint32_t
 // summation index when it is long, so that every CU gets a tile.
 void gemm_sq(const Ctx& c, const double* G, uint32_t s, const double* X, double* C, uint32_t n,
              bool with_done) {
-  if (s < 512) {
-    gemm(c, G, s, X, kBlock, C, kBlock, s, s, n, with_done);
-    return;
-  }
-  const uint32_t nks = cdiv(s, kSplitK);
-  double* P = c.d(c.SL->skpart);
+  const uint32_t nks = s >= 512 ? cdiv(s, kSplitK) : 1;
+  // one slice: the kernel's partial layout (rows of 64) is C itself
+  double* P = nks > 1 ? c.d(c.SL->skpart) : C;
   hipLaunchKernelGGL(k_gemm_splitk, dim3(cdiv(s, 64), nks), dim3(256), 0, c.st, G, s, X, kBlock, P, s,
                      s, n, c.stat(with_done));
-  hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv((uint64_t)s * 64, 256)), dim3(256), 0, c.st, P, nks, s,
-                     C, kBlock, c.stat(with_done));
+  if (nks > 1)
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv((uint64_t)s * 64, 256)), dim3(256), 0, c.st, P, nks,
+                       s, C, kBlock, c.stat(with_done));
 }
 
 void jacobi(const Ctx& c, const double* G, uint32_t nchunk, uint32_t n, double* V, double* lam,
@@ -1149,16 +1184,17 @@ void jacobi(const Ctx& c, const double* G, uint32_t nchunk, uint32_t n, double* 
 double* orthonormalise(const Ctx& c, double* X, double* Y, uint32_t M, uint32_t n, int passes,
                        bool with_done) {
   Status sd = c.stat(with_done);
-  uint32_t nchunk = cdiv(M, 256);
+  uint32_t nchunk = cdiv(M, 32);
   if (nchunk > 64) nchunk = 64;
   uint32_t rows = cdiv(M, nchunk);
+  nchunk = cdiv(M, rows);
   double* B = c.d(c.SL->H);
   double* src = X;
   double* dst = Y;
   for (int pass = 0; pass < passes; ++pass) {
     hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, src, kBlock, src, kBlock, M, n,
                        rows, c.d(c.SL->part), sd);
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, c.st, c.d(c.SL->part), nchunk, n,
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, c.st, c.d(c.SL->part), nchunk, n,
                        pass == 0 ? 1e-15 : 0.0, B, sd);
     gemm(c, src, kBlock, B, n, dst, kBlock, M, n, n, with_done);
     double* t = src;
@@ -1217,9 +1253,10 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
     z = orthonormalise(c, z, w, s, b, 2, true);   // result back in z
     w = other(z, nullptr);
     gemm_sq(c, G, s, z, w, b, true);               // w = G z
-    uint32_t nchunk = cdiv(s, 256);
+    uint32_t nchunk = cdiv(s, 32);
     if (nchunk > 64) nchunk = 64;
     uint32_t rows = cdiv(s, nchunk);
+    nchunk = cdiv(s, rows);
     hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, z, kBlock, w, kBlock, s, b, rows,
                        H, sd);
     jacobi(c, H, nchunk, b, VH, lamH, tags + kTagRR, 0x52520000 | (int32_t)b, true, (int)R, 1e-28);
