@@ -1,0 +1,116 @@
+"""GPU tests of the serving loop: a window's result is the same alone and in a
+mix of concurrent windows (bit for bit: every window has its own
+workspaces and the kernels are deterministic); warm-started windows follow
+the oracle's own chain (a stream's first window: HOSVD + sweeps; later
+windows: time-mode update from the previous host/metric factors, then
+sweeps); the HBM budget limits what is in flight."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mach as O
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+RANKS = (4, 2, 4)
+P = 0.3
+COLD, WARM = 3, 2
+
+
+def _requests():
+    reqs = []
+    hosts = {0: 16, 1: 24, 2: 16}
+    Ts = [256, 320, 288, 352, 300, 260]
+    rid = 0
+    for w in range(2):
+        for s in range(3):
+            reqs.append(synth.ServingRequest(rid, 0.0005 * rid, s, w, hosts[s], Ts[rid], 7000 + s))
+            rid += 1
+    return reqs
+
+
+def _windows(reqs):
+    import torch
+    from paper_0909_4969_amd.serve import Window
+    out, host = [], {}
+    for r in reqs:
+        X = synth.serving_window(r, metrics=8, ranks=RANKS)
+        host[r.req_id] = X
+        out.append(Window(r.req_id, r.stream_id, r.window_id, r.arrival_s, torch.from_numpy(X).cuda(), r.seed))
+    return out, host
+
+
+def _engine(**kw):
+    from paper_0909_4969_amd.serve import Engine, ServeConfig
+    cfg = ServeConfig(ranks=RANKS, p=P, sweeps_cold=COLD, sweeps_warm=WARM, **kw)
+    return Engine(cfg)
+
+
+def test_alone_equals_mix():
+    reqs = _requests()
+    wins, _ = _windows(reqs)
+    say("serve mix", len(wins))
+    mix = _engine(max_active=6, hip_streams=3).run(wins, realtime=False)
+    assert any(r.warm for r in mix) and any(not r.warm for r in mix)
+    for s in range(3):
+        say("serve alone stream", s)
+        alone = _engine(max_active=1, hip_streams=1).run([w for w in wins if w.stream_id == s],
+                                                         realtime=False)
+        for a in alone:
+            m = mix[a.req_id]
+            assert m.req_id == a.req_id and m.warm == a.warm and m.nnz == a.nnz
+            for fa, fm in zip(a.factors, m.factors):
+                assert bool((fa == fm).all()), (a.req_id, "factor differs")
+            assert bool((a.core == m.core).all()), (a.req_id, "core differs")
+            assert a.fit == m.fit
+
+
+def test_warm_chain_matches_oracle():
+    reqs = _requests()
+    wins, host = _windows(reqs)
+    say("serve oracle chain")
+    res = _engine(max_active=4, hip_streams=2).run(wins, realtime=False)
+    prev = {}
+    for r in sorted(reqs, key=lambda q: (q.stream_id, q.window_id)):
+        g = res[r.req_id]
+        Xh = O.sampled_tensor(host[r.req_id], P, r.seed, r.window_id)
+        n2 = float(np.sum(Xh * Xh))
+        if r.stream_id in prev:
+            assert g.warm
+            A = [prev[r.stream_id][0], prev[r.stream_id][1], np.zeros((r.T, RANKS[2]))]
+            A, tr = O.hooi_sweep(Xh, A, RANKS, first_mode=2)
+            sweeps = WARM
+        else:
+            assert not g.warm
+            A = O.hosvd_factors(Xh, RANKS)
+            sweeps = COLD
+        for _ in range(sweeps):
+            A, tr = O.hooi_sweep(Xh, A, RANKS)
+        prev[r.stream_id] = A
+        fit_o = O.fit_from_norms(n2, tr[-1])
+        A_g = [f.cpu().numpy() for f in g.factors]
+        for n in range(3):
+            s = O.sin_theta(A[n], A_g[n])
+            say(f"  window {r.req_id} mode {n}: sin_theta {s:.2e}")
+            assert s <= 1e-4, (r.req_id, n, s)
+        assert abs(g.fit - fit_o) < 1e-5, (g.fit, fit_o)
+        G_o = O.core(Xh, A_g)
+        np.testing.assert_allclose(g.core.cpu().numpy(), G_o, rtol=0, atol=2e-5 * np.abs(G_o).max())
+
+
+def test_hbm_budget_limits_inflight():
+    reqs = _requests()
+    wins, _ = _windows(reqs)
+    eng = _engine(max_active=6, hip_streams=3)
+    fps = [eng.footprint(w.X.shape) for w in wins]
+    eng.cfg.hbm_budget = max(fps) + min(fps) // 2      # room for one window at a time
+    say("serve budget", eng.cfg.hbm_budget)
+    res = eng.run(wins, realtime=False)
+    spans = sorted((r.admit_s, r.done_s) for r in res)
+    for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
+        assert a1 >= d0, "two windows were in flight under a one-window budget"
+    eng.cfg.hbm_budget = min(fps) - 1
+    from paper_0909_4969_amd import mach as M
+    with pytest.raises(M.MachError):
+        eng.run(wins[:1], realtime=False)
