@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=20262)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="windows of the serving run (0: skip it)")
     return ap.parse_args()
 
 
@@ -98,6 +100,74 @@ def cpu_baseline(X, p, seed, ranks, sweeps, cpu_sweeps, nnz):
                    f"{cpu_sweeps} of {sweeps} sweeps timed ({per_sweep:.3f}s each) and the rest "
                    f"extrapolated; job {t_job:.1f}s"),
     }
+
+
+def device_windows(reqs, metrics=16, ranks=(8, 4, 16), rel_noise=0.01):
+    """Serving windows built on the device (seeded torch generators): per
+    stream a Gaussian core and host/metric factors, per window a Gaussian
+    time factor; X = Tucker product + noise of sigma = rel_noise ||X|| /
+    sqrt(N), float32.  Same recipe as the host generator of the tests, drawn
+    on the GPU so that hundreds of windows are ready in HBM in a second."""
+    import torch
+    from paper_0909_4969_amd.serve import Window
+    per_stream = {}
+    out = []
+    for r in reqs:
+        if r.stream_id not in per_stream:
+            g = torch.Generator(device="cuda").manual_seed(r.seed)
+            core = torch.randn(ranks, generator=g, device="cuda")
+            A_h = torch.randn(r.hosts, ranks[0], generator=g, device="cuda") / r.hosts ** 0.5
+            A_m = torch.randn(metrics, ranks[1], generator=g, device="cuda") / metrics ** 0.5
+            T2 = torch.einsum("abc,ha,mb->hmc", core, A_h, A_m).reshape(r.hosts * metrics, ranks[2])
+            per_stream[r.stream_id] = T2.contiguous()
+        g = torch.Generator(device="cuda").manual_seed(r.seed * 1000003 + r.window_id)
+        A_t = torch.randn(r.T, ranks[2], generator=g, device="cuda") / r.T ** 0.5
+        X = (per_stream[r.stream_id] @ A_t.t().contiguous()).reshape(r.hosts, metrics, r.T)
+        sigma = rel_noise * float(X.norm()) / X.numel() ** 0.5
+        X = X + sigma * torch.randn(X.shape, generator=g, device="cuda")
+        out.append(Window(r.req_id, r.stream_id, r.window_id, r.arrival_s, X.contiguous(), r.seed))
+    return out
+
+
+def serving_bench(n_requests, prec_modes):
+    """Config-5 serving: Poisson arrivals (200/s) of hosts x 16 x T windows
+    from 8 streams (hosts in {32, 64, 128} per stream, T uniform in
+    [1024, 16384]), p = 0.05, ranks (8, 4, 16); a stream's first window runs
+    HOSVD + 6 sweeps, later windows the warm time-mode update + 3 sweeps.
+    Continuous batching (8 windows in flight over 4 HIP streams) against
+    plain per-request solves (one window at a time)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0909_4969_amd import mach as M
+    from paper_0909_4969_amd.serve import Engine, ServeConfig, latency_summary
+    reqs = synth.serving_stream(n_requests=n_requests)
+    wins = device_windows(reqs)
+    torch.cuda.synchronize()
+    out = {"workload": f"poisson-200/s {n_requests} windows, 8 streams, hosts x 16 x T, "
+                       f"T in [1024,16384], p=0.05, ranks (8,4,16)",
+           "windows_resident_in_hbm": True}
+    modes = [("continuous_f32", dict(max_active=8, hip_streams=4), M.MACH_F32),
+             ("per_request_f32", dict(max_active=1, hip_streams=1), M.MACH_F32)]
+    modes += [(f"continuous_{name}", dict(max_active=8, hip_streams=4), code) for name, code in prec_modes]
+    for name, kw, prec in modes:
+        cfg = ServeConfig(ranks=(8, 4, 16), p=0.05, sweeps_cold=6, sweeps_warm=3, prec=prec,
+                          hbm_budget=64 << 30, **kw)
+        eng = Engine(cfg)
+        eng.run(wins[:8], realtime=False)            # warm-up: kernels, allocator
+        eng.resident.clear()
+        torch.cuda.synchronize()
+        res = eng.run(wins, realtime=True)
+        summ = latency_summary(res)
+        work = sum(r.nnz * ((cfg.sweeps_warm + 1.0 / 3.0) if r.warm else cfg.sweeps_cold) for r in res)
+        summ["nnz_per_s"] = work / summ["span_s"]
+        summ["mean_fit"] = float(np.mean([r.fit for r in res]))
+        summ["warm_windows"] = sum(1 for r in res if r.warm)
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+        del eng, res
+        torch.cuda.synchronize()
+    return out
 
 
 def main():
@@ -205,6 +275,8 @@ def main():
         "sweep_only_nnz_per_s": round(nnz / (phase["sweep_ms"] / 1e3), 1),
         "roofline": roofline,
     }
+    if args.serve_requests > 0:
+        out["serving"] = serving_bench(args.serve_requests, [])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X_np, p, args.seed, ranks, sweeps, args.cpu_sweeps, nnz)
     print(json.dumps(out), flush=True)
