@@ -47,7 +47,63 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="windows of the serving run (0: skip it)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times (the "
+                         "reference kernel for scaling HBM counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the TTM traffic summary from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this script with --copy-mib, and exit")
     return ap.parse_args()
+
+
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "ttm_traffic_monitoring-128x16x16384.json")
+
+
+def pmc_summary(fetch_dir, write_dir, copy_mib):
+    """Per-launch HBM bytes of the two sparse TTM passes from rocprofv3
+    counter CSVs: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over
+    the dispatches of each kernel, each scaled by (true bytes of the
+    reference copy) / (what the same counter reads for that copy)."""
+    import csv
+    import glob
+    import re
+
+    def read(d, counter):
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        # the reference copy: the copy kernel dispatches of the largest grid
+        big = max(int(r["Grid_Size"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
+        acc = {}
+        for r in rows:
+            n = r["Kernel_Name"]
+            m = re.search(r"k_spc<(\d), (\d+), (\d+), (\d)>", n)
+            key = None
+            if m:
+                key = "ttm_tail_cols" if m.group(4) == "1" else "ttm_head_rows"
+            elif "copyBuffer" in n and int(r["Grid_Size"]) == big:
+                key = "copy"
+            if key:
+                acc.setdefault(key, []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+    true_bytes = copy_mib * (1 << 20)
+    f_scale = true_bytes / (fetch["copy"] * 1024.0)
+    w_scale = true_bytes / (write["copy"] * 1024.0)
+    out = {"ttm_source_digest": kernel_source_digest(),
+           "fetch_kib_per_dispatch": {k: round(v, 1) for k, v in fetch.items()},
+           "write_kib_per_dispatch": {k: round(v, 1) for k, v in write.items()},
+           "copy_reference_bytes": true_bytes,
+           "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+           "bytes_per_launch": {k: int(fetch[k] * 1024 * f_scale + write[k] * 1024 * w_scale)
+                                for k in ("ttm_head_rows", "ttm_tail_cols")},
+           "commands": [
+               "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE "
+               "--output-format csv -d $R/gpurun_out/pmc_fetch -o run -- python3 $R/bench.py --steps 1 "
+               "--warmup 1 --no-cpu-baseline --serve-requests 0 --copy-mib 256",
+               "(the same with --pmc WRITE_SIZE and -d $R/gpurun_out/pmc_write)",
+               "python3 bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write --copy-mib 256"]}
+    return out
 
 
 def kernel_source_digest():
@@ -60,9 +116,8 @@ def kernel_source_digest():
 def traffic_from_profiles(which):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "ttm_traffic_monitoring-128x16x16384.json")
     try:
-        with open(path) as f:
+        with open(TRAFFIC_JSON) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
@@ -172,6 +227,12 @@ def serving_bench(n_requests, prec_modes):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        d = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_mib or 256)
+        with open(TRAFFIC_JSON, "w") as f:
+            json.dump(d, f, indent=1)
+        print(json.dumps(d))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU sharding is a design, not built)"}))
@@ -275,6 +336,13 @@ def main():
         "sweep_only_nnz_per_s": round(nnz / (phase["sweep_ms"] / 1e3), 1),
         "roofline": roofline,
     }
+    if args.copy_mib > 0:
+        a = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.serve_requests > 0:
         out["serving"] = serving_bench(args.serve_requests, [])
     if not args.no_cpu_baseline:
