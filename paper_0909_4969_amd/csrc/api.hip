@@ -258,6 +258,46 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
     mb.cO = 1; mb.cI = I[a]; mb.cQ = I[b] * S.KH;
     mb.O = R(a); mb.Q = S.KH;
   }
+  // Column strides of the other modes in Y_(k): C order over the head modes
+  // (KH) and over the tail modes (KT); a contracted second mode of the own
+  // side comes first, with stride KT (head side) or KH (tail side).
+  {
+    uint32_t stH[kMaxD] = {}, stT[kMaxD] = {};
+    uint32_t acc = 1;
+    for (int j = h - 1; j >= 0; --j) { stH[j] = acc; acc *= R(j); }
+    acc = 1;
+    for (int j = d - 1; j >= h; --j) { stT[j] = acc; acc *= R(j); }
+    for (int k = 0; k < d; ++k) {
+      ModePlan& m = S.mp[k];
+      const bool head = k < h;
+      for (int j = 0; j < d; ++j) {
+        if (j == k) continue;
+        const bool jhead = j < h;
+        if (jhead == head) m.kst[j] = head ? S.KT : S.KH;   // the contracted partner
+        else m.kst[j] = jhead ? stH[j] : stT[j];
+      }
+    }
+  }
+  // Column strides of the other modes in Y_(k): C order over the head modes
+  // (KH) and over the tail modes (KT); a contracted second mode of the own
+  // side comes first, with stride KT (head side) or KH (tail side).
+  {
+    uint32_t stH[kMaxD] = {}, stT[kMaxD] = {};
+    uint32_t acc = 1;
+    for (int j = h - 1; j >= 0; --j) { stH[j] = acc; acc *= R(j); }
+    acc = 1;
+    for (int j = d - 1; j >= h; --j) { stT[j] = acc; acc *= R(j); }
+    for (int k = 0; k < d; ++k) {
+      ModePlan& m = S.mp[k];
+      const bool head = k < h;
+      for (int j = 0; j < d; ++j) {
+        if (j == k) continue;
+        const bool jhead = j < h;
+        if (jhead == head) m.kst[j] = head ? S.KT : S.KH;   // the contracted partner
+        else m.kst[j] = jhead ? stH[j] : stT[j];
+      }
+    }
+  }
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -275,6 +315,9 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
     if (m.s <= (uint32_t)kSmallEig) {
       m.V = take((size_t)m.s * m.s * 8);
       m.lam = take((size_t)m.s * 8);
+      if (m.kside)
+        for (int j = 0; j < d; ++j)
+          if (j != k) m.snap[j] = take((size_t)I[j] * 16 * 4);
     } else {
       m.Q64 = take((size_t)m.s * kBlock * 8);
       m.lam = take((size_t)kBlock * 8);

@@ -37,10 +37,11 @@ hipError_t launch_gram_tail_sparse(const ShapeInfo& si, const SparsePtrs& sp, co
 namespace {
 
 constexpr int kMaxSweeps = 40;
-// Jacobi stops when the off-diagonal Frobenius norm is below 1e-10 of the
-// diagonal's: eigenvector errors are then below 1e-10 / (relative gap),
-// far under the float32 rounding of the Gram that feeds the solve.
-constexpr double kOffTol2 = 1e-20;
+// Jacobi stops when the off-diagonal Frobenius norm of the leading rows is
+// below 1e-8 of their diagonal's: the eigenvectors are then exact for a
+// matrix within 1e-8 (relative) of the Gram, whose own float32 rounding is
+// about 1e-7, so a tighter test would only resolve rounding noise.
+constexpr double kOffTol2 = 1e-16;
 
 __device__ __forceinline__ void jpair(int r, int k, int np, int* p, int* q) {
   int m = np - 1, a, b;
@@ -50,6 +51,20 @@ __device__ __forceinline__ void jpair(int r, int k, int np, int* p, int* q) {
   } else {
     a = (r + k) % m;
     b = (r - k + m) % m;
+  }
+  *p = a < b ? a : b;
+  *q = a < b ? b : a;
+}
+
+// The same pairing with the size a compile-time constant (the modulo by
+// NP - 1 becomes a multiply and shift), for the per-round index math.
+template <int NP>
+__device__ __forceinline__ void jpair_c(int r, int k, int* p, int* q) {
+  constexpr int m = NP - 1;
+  int a = (r + k) % m, b = (r - k + m) % m;
+  if (k == 0) {
+    a = r;
+    b = m;
   }
   *p = a < b ? a : b;
   *q = a < b ? b : a;
@@ -129,15 +144,54 @@ __device__ void block_sum2n(double& a, double& b, double (*red)[16]) {
   __syncthreads();
 }
 
-// Loads V (warm start, n x n row-major) or the identity into L.V and, when
-// warm, replaces L.A = G by V^T G V.  Expects L.A = G (padded with zeros).
-template <int NP, int NT>
-__device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin) {
+// D = op(A) B for NP x NP matrices in LDS (op(A) = A^T when TA), each of
+// the first (NP/4)^2 threads accumulating a 4 x 4 block in float64; D may
+// alias A or B (every read completes before the first write).
+template <int NP, int NT, bool TA>
+__device__ void lds_gemm(double (*A)[NP + 1], double (*B)[NP + 1], double (*D)[NP + 1]) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < NP * NP; e += NT) {
-    int x = e / NP, y = e % NP;
-    L.V[x][y] = (warm && x < n && y < n) ? Vin[x * n + y] : (x == y ? 1.0 : 0.0);
-  }
+  const bool own = tid < (NP / 4) * (NP / 4);
+  const int bx = (tid / (NP / 4)) * 4, by = (tid % (NP / 4)) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  if (own)
+    for (int z = 0; z < NP; ++z) {
+      double u[4], w[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        u[i] = TA ? A[z][bx + i] : A[bx + i][z];
+        w[i] = B[z][by + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
+    }
+  __syncthreads();
+  if (own)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) D[bx + i][by + j] = acc[i][j];
+  __syncthreads();
+}
+
+// Sets the start basis L.V — the identity, the warm start Vin (n x n
+// row-major, when warm), or the one already in L.V (in_lds) — and, unless it
+// is the identity, replaces L.A = G by V^T G V.  Expects L.A = G (padded
+// with zeros).
+template <int NP, int NT>
+__device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin, bool in_lds = false) {
+  const int tid = threadIdx.x;
+  if (!in_lds)
+    for (int e = tid; e < NP * NP; e += NT) {
+      int x = e / NP, y = e % NP;
+      L.V[x][y] = (warm && x < n && y < n) ? Vin[x * n + y] : (x == y ? 1.0 : 0.0);
+    }
+  warm = warm || in_lds;
   for (int e = tid; e < (NP - 1) * (NP / 2); e += NT) {
     int r = e / (NP / 2), k = e % (NP / 2), p, q;
     jpair(r, k, NP, &p, &q);
@@ -230,7 +284,8 @@ __device__ int jacobi_core(JacLds<NP>& L, int n, int rtop, bool* conv, double to
     if (*conv || sweep == kMaxSweeps) break;
     for (int r = 0; r < ROUNDS; ++r) {
       if (tid < PAIRS) {
-        int p = L.tp[r][tid], q = L.tq[r][tid];
+        int p, q;
+        jpair_c<NP>(r, tid, &p, &q);
         double apq = L.A[p][q], app = L.A[p][p], aqq = L.A[q][q];
         double c = 1.0, sn = 0.0, t = 0.0;
         if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * (fabs(app) + fabs(aqq))) {
@@ -246,7 +301,9 @@ __device__ int jacobi_core(JacLds<NP>& L, int n, int rtop, bool* conv, double to
       __syncthreads();
       for (int blk = tid; blk < PAIRS * PAIRS; blk += NT) {
         int ia = blk / PAIRS, ib = blk % PAIRS;
-        int pa = L.tp[r][ia], qa = L.tq[r][ia], pb = L.tp[r][ib], qb = L.tq[r][ib];
+        int pa, qa, pb, qb;
+        jpair_c<NP>(r, ia, &pa, &qa);
+        jpair_c<NP>(r, ib, &pb, &qb);
         if (ia == ib) {
           double ta = L.rt[ia], apq = L.A[pa][qa];
           L.A[pa][pa] -= ta * apq;
@@ -266,7 +323,8 @@ __device__ int jacobi_core(JacLds<NP>& L, int n, int rtop, bool* conv, double to
       }
       for (int it = tid; it < NP * PAIRS; it += NT) {
         int x = it / PAIRS, ib = it % PAIRS;
-        int pb = L.tp[r][ib], qb = L.tq[r][ib];
+        int pb, qb;
+        jpair_c<NP>(r, ib, &pb, &qb);
         double cb = L.rc[ib], sb = L.rs[ib];
         double v1 = L.V[x][pb], v2 = L.V[x][qb];
         L.V[x][pb] = cb * v1 - sb * v2;
@@ -328,6 +386,48 @@ __global__ __launch_bounds__(NT) void k_jacobi_small(JacArgs a) {
   }
 }
 
+// Column-side warm start.  The eigenvectors of G = Y_(k)^T Y_(k) live in the
+// coordinates of the other modes' factor columns (Y_(k) = Xhat_(k) times the
+// Kronecker product of the other factors), and those columns rotate from one
+// sweep to the next, mostly within groups of nearly equal singular values, so
+// the previous eigenbasis V_old is not a good start as it stands.  With
+// C_j = A_j,old^T A_j,new (R_j x R_j) for every other mode j, A_j,new ~=
+// A_j,old C_j, hence Y_new ~= Y_old P with P = kron_j C_j (in the column
+// order of Y_(k)), G_new ~= P^T G_old P, and P^T V_old is the previous
+// eigenbasis in the current coordinates.  P is orthogonal up to how far the
+// factor subspaces moved; Newton-Schulz steps restore orthogonality.
+// part[(slot * 256 + a * 16 + b) * kCtcChunks + chunk] = sum over the chunk's
+// rows i of old[i][a] * cur[i][b] (float32 factors I_j x 16, float64 sums).
+constexpr uint32_t kCtcChunks = 128;
+
+struct CtcArgs {
+  const float* old[3];
+  const float* cur[3];
+  uint32_t I[3];
+  uint32_t nch[3];        // chunks of slot j: ctc_chunks(I_j)
+  int n;
+};
+
+__host__ __device__ inline uint32_t ctc_chunks(uint32_t I) {
+  uint32_t c = (I + 127) / 128;
+  return c < 1 ? 1 : (c > kCtcChunks ? kCtcChunks : c);
+}
+
+__global__ __launch_bounds__(256) void k_ctc_partial(CtcArgs a, double* __restrict__ part, Status s) {
+  if (s.skip()) return;
+  const int slot = blockIdx.y;
+  if (slot >= a.n || blockIdx.x >= a.nch[slot]) return;
+  const uint32_t I = a.I[slot];
+  const uint32_t rows = (I + a.nch[slot] - 1) / a.nch[slot];
+  const uint32_t i0 = blockIdx.x * rows, i1 = min(I, i0 + rows);
+  const int aa = threadIdx.x >> 4, bb = threadIdx.x & 15;
+  const float* po = a.old[slot];
+  const float* pc = a.cur[slot];
+  double acc = 0.0;
+  for (uint32_t i = i0; i < i1; ++i) acc = fma((double)po[(size_t)i * 16 + aa], (double)pc[(size_t)i * 16 + bb], acc);
+  part[((size_t)slot * 256 + threadIdx.x) * kCtcChunks + blockIdx.x] = acc;   // chunks < nch[slot] used
+}
+
 // One mode update of a HOOI sweep, sides up to 64, in one workgroup:
 // G = sum of the Gram partials (fixed order); warm-started Jacobi; the
 // eigenpairs sorted and kept for the next sweep.  Row-side Gram: the top R
@@ -338,6 +438,9 @@ struct SolveArgs {
   const double* part;
   uint32_t nchunk, s, I, R;
   int kside;
+  const double* ctc;      // column side: C_j partials of the other modes (k_ctc_partial), or null
+  int nother;              // other modes: ranks, column strides in Y_(k), C_j chunks
+  uint32_t oR[3], ost[3], onch[3];
   double* V;
   double* lam;
   int32_t* tag;
@@ -356,21 +459,81 @@ __global__ __launch_bounds__(NT) void k_mode_solve(SolveArgs a) {
   __shared__ double sgn[16];
   __shared__ int col_of_rank[16];
   const int n = (int)a.s, tid = threadIdx.x;
-  const uint32_t n2 = a.s * a.s;
   for (int e = tid; e < NP * NP; e += NT) {
     int x = e / NP, y = e % NP;
     double g = 0.0;
-    if (x < n && y < n)
-      for (uint32_t c = 0; c < a.nchunk; ++c) g += a.part[(size_t)c * n2 + x * n + y];
+    if (x < n && y < n) {
+      const double* p = a.part + (size_t)(x * n + y) * a.nchunk;
+#pragma unroll 8
+      for (uint32_t c = 0; c < a.nchunk; ++c) g += p[c];
+    }
     L.A[x][y] = g;
   }
   __syncthreads();
-  const bool warm = (*a.tag == a.tagval);
-  jacobi_setup<NP, NT>(L, n, warm, a.V);
+  bool warm = (*a.tag == a.tagval);
+  if (warm && a.ctc) {
+    __shared__ double Cj[3][16][17];
+    for (int e = tid; e < a.nother * 256; e += NT) {
+      const double* p = a.ctc + (size_t)e * kCtcChunks;
+      const uint32_t nc = a.onch[e >> 8];
+      double v = 0.0;
+#pragma unroll 8
+      for (uint32_t c = 0; c < nc; ++c) v += p[c];
+      Cj[e >> 8][(e >> 4) & 15][e & 15] = v;
+    }
+    for (int e = tid; e < NP * NP; e += NT) {
+      const int x = e / NP, y = e % NP;
+      L.V[x][y] = (x < n && y < n) ? a.V[x * n + y] : (x == y ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    // P[x][y] = prod_j C_j[(x / st_j) % R_j][(y / st_j) % R_j]
+    for (int e = tid; e < NP * NP; e += NT) {
+      const int x = e / NP, y = e % NP;
+      double v = (x == y) ? 1.0 : 0.0;
+      if (x < n && y < n) {
+        v = 1.0;
+        for (int j = 0; j < a.nother; ++j)
+          v *= Cj[j][(x / a.ost[j]) % a.oR[j]][(y / a.ost[j]) % a.oR[j]];
+      }
+      L.W[x][y] = v;
+    }
+    __syncthreads();
+    // V <- P^T V_old
+    lds_gemm<NP, NT, true>(L.W, L.V, L.V);
+    // Newton-Schulz steps towards the nearest orthogonal matrix,
+    // V <- V (3 I - V^T V) / 2, until ||V^T V - I||_F <= 1e-11 (at most 10;
+    // if the factors moved so far that it does not get there, cold start).
+    bool ortho = false;
+    for (int it = 0; it < 11; ++it) {
+      lds_gemm<NP, NT, true>(L.V, L.V, L.W);
+      double dev2 = 0.0, unused = 0.0;
+      for (int e = tid; e < NP * NP; e += NT) {
+        const int x = e / NP, y = e % NP;
+        const double d = L.W[x][y] - (x == y ? 1.0 : 0.0);
+        dev2 = fma(d, d, dev2);
+        L.W[x][y] = 0.5 * ((x == y ? 3.0 : 0.0) - L.W[x][y]);
+      }
+      block_sum2n<NT>(dev2, unused, L.red);
+      if (dev2 <= 1e-22) {
+        ortho = true;
+        break;
+      }
+      if (it == 10) break;
+      lds_gemm<NP, NT, false>(L.V, L.W, L.V);
+    }
+    if (!ortho) {
+      for (int e = tid; e < NP * NP; e += NT) L.V[e / NP][e % NP] = (e / NP == e % NP) ? 1.0 : 0.0;
+      __syncthreads();
+    }
+    warm = ortho;
+    jacobi_setup<NP, NT>(L, n, ortho, nullptr, true);
+  } else {
+    jacobi_setup<NP, NT>(L, n, warm, a.V);
+  }
   bool conv;
   int used = jacobi_core<NP, NT>(L, n, (int)a.R, &conv);
   jacobi_sort_store<NP, NT>(L, n, a.lam, a.V);
-  if (tid == 0 && a.stats) *a.stats = used + (warm ? 1000 : 0);
+  if (tid == 0 && a.stats) *a.stats = used + (warm && a.ctc ? 2000 : warm ? 1000 : 0);
   if (tid < n && L.rk[tid] < (int)a.R) col_of_rank[L.rk[tid]] = tid;
   __syncthreads();
   if (tid == 0) {
@@ -641,16 +804,6 @@ __global__ __launch_bounds__(256) void k_atb_partial(const double* __restrict__ 
       uint32_t x = tx * 4 + i, y = ty * 4 + j;
       if (x < n && y < n) part[(size_t)(x * n + y) * gridDim.x + blockIdx.x] = acc[i][j];
     }
-}
-
-__global__ void k_small_reduce(const double* __restrict__ part, uint32_t nchunk, uint32_t n2,
-                               double* __restrict__ out, Status s) {
-  if (s.skip()) return;
-  uint32_t e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= n2) return;
-  double acc = 0.0;
-  for (uint32_t c = 0; c < nchunk; ++c) acc += part[(size_t)c * n2 + e];
-  out[e] = acc;
 }
 
 // C[M x N] partials of A[M x K] * B[K x N] (row-major, N <= 64) for long K:
@@ -1322,7 +1475,6 @@ hipError_t launch_solver_init(const SolverLayout& SL, char* ws, hipStream_t st) 
 
 hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k,
                               double* A_out, const SampleHdr* hdr, hipStream_t st) {
-  (void)si;
   Ctx c{&SL, ws, hdr, st};
   const ModePlan& m = SL.mp[k];
   int32_t tagval = 0x4d000000 | (k << 16) | (int32_t)m.s;
@@ -1332,17 +1484,32 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     if (e != hipSuccess) return e;
     SolveArgs a;
     a.part = c.d(SL.Gpart);
-    if (nchunk > 4) {
-      hipLaunchKernelGGL(k_small_reduce, dim3(cdiv(m.s * m.s, 256)), dim3(256), 0, st, c.d(SL.Gpart),
-                         nchunk, m.s * m.s, c.d(SL.G), c.stat());
-      a.part = c.d(SL.G);
-      nchunk = 1;
+    a.ctc = nullptr;
+    a.nother = 0;
+    if (m.kside) {
+      CtcArgs ca{};
+      for (int j = 0; j < si.d; ++j) {
+        if (j == k) continue;
+        ca.old[ca.n] = (const float*)(ws + m.snap[j]);
+        ca.cur[ca.n] = (const float*)(ws + SL.af[j]);
+        ca.I[ca.n] = si.dims[j];
+        ca.nch[ca.n] = ctc_chunks(si.dims[j]);
+        a.onch[ca.n] = ca.nch[ca.n];
+        a.oR[ca.n] = SL.mp[j].R;
+        a.ost[ca.n] = m.kst[j];
+        ++ca.n;
+      }
+      a.nother = ca.n;
+      a.ctc = c.d(SL.part);
+      hipLaunchKernelGGL(k_ctc_partial, dim3(kCtcChunks, ca.n), dim3(256), 0, st, ca, c.d(SL.part),
+                         c.stat());
     }
     a.nchunk = nchunk;
     a.s = m.s;
     a.I = m.I;
     a.R = m.R;
     a.kside = m.kside;
+
     a.V = c.d(m.V);
     a.lam = c.d(m.lam);
     a.tag = c.tags() + k;
@@ -1359,6 +1526,12 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     else
       hipLaunchKernelGGL((k_mode_solve<64, 1024>), dim3(1), dim3(1024), 0, st, a);
     if (m.kside) {
+      for (int j = 0; j < si.d; ++j) {
+        if (j == k) continue;
+        e = hipMemcpyAsync(ws + m.snap[j], ws + SL.af[j], (size_t)si.dims[j] * 16 * 4,
+                           hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+      }
       uint32_t nwg = cdiv(m.I, 256);
       double* part = c.d(SL.part);
       hipLaunchKernelGGL(k_bp_tall, dim3(nwg), dim3(256), 0, st, (const float*)(ws + m.ybuf), m.O, m.I,

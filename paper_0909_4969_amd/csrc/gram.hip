@@ -26,7 +26,8 @@ struct GramArgs {
   int kside;              // 1: column side (J x J), 0: row side (I x I)
   uint32_t X, Z;          // Gram side and summation length
   uint32_t zchunk;        // summation slice per workgroup
-  double* part;           // [chunk][X][X]
+  double* part;           // [X][X][chunk] (chunk-minor)
+  uint32_t nz;            // number of slices (chunks)
   const int32_t* st_solver;
   const SampleHdr* hdr;
 };
@@ -61,7 +62,8 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a, Load ld) {
   __shared__ float Mx[32][65];
   __shared__ float My[32][65];
   const uint32_t x0 = blockIdx.x * 64, y0 = blockIdx.y * 64;
-  const uint32_t zc0 = blockIdx.z * a.zchunk;
+  const uint32_t zb = blockIdx.z;
+  const uint32_t zc0 = zb * a.zchunk;
   const uint32_t zc1 = min(a.Z, zc0 + a.zchunk);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double acc[4][4];
@@ -115,24 +117,26 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a, Load ld) {
       for (int j = 0; j < 4; ++j) acc[i][j] += (double)c[i][j];
     __syncthreads();
   }
-  double* out = a.part + (size_t)blockIdx.z * a.X * a.X;
+  double* out = a.part;   // chunk-minor: entry (x, y) of slice zb
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       uint32_t x = x0 + tx * 4 + i, y = y0 + ty * 4 + j;
-      if (x < a.X && y < a.X) out[(size_t)x * a.X + y] = acc[i][j];
+      if (x < a.X && y < a.X) out[((size_t)x * a.X + y) * a.nz + zb] = acc[i][j];
     }
 }
 
-// G = sum over chunks of part (fixed order).
+// G = sum over chunks of part (chunk-minor, fixed order).
 __global__ void k_gram_reduce(const double* __restrict__ part, uint32_t nchunk, uint32_t n2,
                               double* __restrict__ G, const SampleHdr* hdr, const int32_t* st_solver) {
   if (hdr->status != 0 || *st_solver != 0) return;
   uint32_t e = blockIdx.x * 256 + threadIdx.x;
   if (e >= n2) return;
+  const double* p = part + (size_t)e * nchunk;
   double s = 0.0;
-  for (uint32_t c = 0; c < nchunk; ++c) s += part[(size_t)c * n2 + e];
+#pragma unroll 8
+  for (uint32_t c = 0; c < nchunk; ++c) s += p[c];
   G[e] = s;
 }
 
@@ -165,6 +169,7 @@ hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream
   nchunk = (a.Z + a.zchunk - 1) / a.zchunk;
   if (nchunk < 1) nchunk = 1;
   if (nchunk == 1) a.part = G;
+  a.nz = nchunk;
   hipLaunchKernelGGL((k_gram<Load>), dim3(tiles, tiles, nchunk), dim3(256), 0, st, a, ld);
   if (nchunk > 1)
     hipLaunchKernelGGL(k_gram_reduce, dim3((uint32_t)((n2 + 255) / 256)), dim3(256), 0, st, a.part,
@@ -402,7 +407,7 @@ hipError_t launch_gram_tail_sparse(const ShapeInfo& si, const SparsePtrs& sp, co
   return hipGetLastError();
 }
 
-// Gram partials of Y_k (dense float32 view): SL.Gpart[c][X][X], c < *nchunk.
+// Gram partials of Y_k (dense float32 view): SL.Gpart[X][X][c], c < *nchunk.
 hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
                                   hipStream_t st, uint32_t* nchunk) {
   const ModePlan& m = SL.mp[k];
@@ -418,6 +423,7 @@ hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, const
   a.st_solver = (const int32_t*)(ws + SL.status);
   a.hdr = hdr;
   *nchunk = gram_slices(a, SL.Gpart_elems);
+  a.nz = *nchunk;
   uint32_t tiles = (a.X + 63) / 64;
   DenseLoad ld{(const float*)(ws + m.ybuf)};
   hipLaunchKernelGGL((k_gram<DenseLoad>), dim3(tiles, tiles, *nchunk), dim3(256), 0, st, a, ld);

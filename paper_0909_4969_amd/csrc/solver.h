@@ -34,6 +34,10 @@ struct ModePlan {
   uint32_t O, Q;           // view of Y_k
   size_t ybuf;             // byte offset of Y_k's buffer (or of TH/TT)
   size_t V, lam, Q64;      // eigen state: V (s x s) or Q64 (s x kBlock)
+  // column side, s <= 64: the other modes' float32 factors at the last solve
+  // (I_j x 16 each) and the stride of each other mode's column index in Y_(k)
+  size_t snap[kMaxD];
+  uint32_t kst[kMaxD];
 };
 
 constexpr uint32_t kBlock = 64;          // subspace block for sides > kSmallEig
