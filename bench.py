@@ -336,6 +336,32 @@ def main():
         "sweep_only_nnz_per_s": round(nnz / (phase["sweep_ms"] / 1e3), 1),
         "roofline": roofline,
     }
+    # Mixed precision on the same window: 20 sweeps after HOSVD with bfloat16
+    # factor entries in the sparse TTM, against the float32 run above.
+    A32 = [a.clone() for a in dec.factors]
+    fit32 = float(dec.fit.item())
+    dec.sample(X, args.seed, 999)
+    dec.hosvd()
+    torch.cuda.synchronize()
+    eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    eb0.record()
+    for _ in range(sweeps):
+        dec.sweep(prec=M.MACH_BF16)
+    eb1.record()
+    torch.cuda.synchronize()
+    if dec.status()[0] != 0:
+        raise SystemExit("device status after the bfloat16 sweeps")
+    import numpy as np
+    sin_max = 0.0
+    for a32, abf in zip(A32, dec.factors):
+        a32, abf = a32.cpu().numpy(), abf.cpu().numpy()
+        sin_max = max(sin_max, float(np.linalg.norm(abf - a32 @ (a32.T @ abf), 2)))
+    out["precision"] = {
+        "f32": {"sweep_ms": round(phase["sweep_ms"], 4), "fit": fit32},
+        "bf16": {"sweep_ms": round(eb0.elapsed_time(eb1) / sweeps, 4), "fit": float(dec.fit.item()),
+                 "max_sin_theta_vs_f32": sin_max},
+        "note": "bf16 = sparse-TTM factor entries rounded to bfloat16, float32 sums, float64 eigensolve",
+    }
     if args.copy_mib > 0:
         a = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -344,7 +370,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if args.serve_requests > 0:
-        out["serving"] = serving_bench(args.serve_requests, [])
+        out["serving"] = serving_bench(args.serve_requests, [("bf16", M.MACH_BF16)])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X_np, p, args.seed, ranks, sweeps, args.cpu_sweeps, nnz)
     print(json.dumps(out), flush=True)

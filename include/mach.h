@@ -99,9 +99,9 @@ mach_status mach_sample(const mach_shape* s, mach_dtype x_dtype, const void* X_d
                         void* ws, size_t ws_bytes, uint64_t nnz_cap, void* stream);
 
 /* Bytes of the solver workspace for shape s and ranks R_1..R_d (host array
- * of d int32).  prec selects the TTM/Gram input precision of
- * mach_hooi_sweep (MACH_F32, MACH_BF16 or MACH_FP8E4M3).  Returns 0 if the
- * arguments are invalid. */
+ * of d int32).  prec is the sparse-TTM factor precision mach_hooi_sweep
+ * will be called with (MACH_F32 or MACH_BF16; the workspace serves both).
+ * Returns 0 if the arguments are invalid or prec is not supported. */
 size_t mach_solver_workspace_bytes(const mach_shape* s, const int32_t* ranks,
                                    mach_dtype prec, uint64_t nnz_cap);
 
@@ -120,10 +120,12 @@ mach_status mach_hosvd(const void* ws_sample, uint64_t nnz_cap, const mach_shape
 
 /* One HOOI sweep (Alg. 2, one pass of the REPEAT body) over modes
  * first_mode..d-1 in order, each update seen by the next.  For mode n:
- * Y = Xhat x_{k != n} A^(k)T (sparse tensor-times-matrix chain, float32 or
- * the mixed precision `prec` with float32 accumulation), the Gram of Y_(n)
- * on its smaller side, its top R_n eigenvectors in float64, and (for the
- * column-side Gram) back-projection and float64 re-orthonormalisation.
+ * Y = Xhat x_{k != n} A^(k)T (sparse tensor-times-matrix chain; factor
+ * entries read as float32 for prec = MACH_F32 or rounded to bfloat16 for
+ * prec = MACH_BF16, products and sums in float32 either way), the Gram of
+ * Y_(n) on its smaller side, its top R_n eigenvectors in float64, and (for
+ * the column-side Gram) back-projection and float64 re-orthonormalisation.
+ * Other prec values return MACH_EUNSUPPORTED.
  * A_dev (host array of d device pointers, I_n x R_n float64) is read and
  * the updated factors written back.  If fit_dev is not NULL, the device
  * double it points to receives 1 - ||Xhat - G x A|| / ||Xhat|| after the

@@ -306,6 +306,7 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   };
   S.status = take(256);
   for (int k = 0; k < d; ++k) S.af[k] = take((size_t)I[k] * 16 * 4);
+  for (int k = 0; k < d; ++k) S.af16[k] = take((size_t)I[k] * 16 * 2);
   S.TH = take((size_t)si.MH * S.KT * 4);
   S.TT = take((size_t)si.MT * S.KH * 4);
   for (int k = 0; k < d; ++k) {
@@ -432,7 +433,7 @@ size_t mach_solver_workspace_bytes(const mach_shape* s, const int32_t* ranks, ma
   ShapeInfo si;
   SolverLayout SL;
   (void)nnz_cap;
-  if (prec != MACH_F32) return 0;
+  if (prec != MACH_F32 && prec != MACH_BF16) return 0;
   if (!make_shape_info(s, &si) || si.d > 4 || !make_solver_layout(si, ranks, &SL)) return 0;
   return SL.total;
 }
@@ -467,7 +468,8 @@ mach_status mach_hooi_sweep(const void* ws_sample, uint64_t nnz_cap, const mach_
                             const int32_t* ranks, double* const* A_dev, mach_dtype prec,
                             int32_t first_mode, void* ws, size_t ws_bytes, double* fit_dev,
                             void* stream) {
-  if (prec != MACH_F32) return MACH_EUNSUPPORTED;
+  if (prec != MACH_F32 && prec != MACH_BF16) return MACH_EUNSUPPORTED;
+  const int bf16 = prec == MACH_BF16;
   Prepared P;
   mach_status rc = prepare(ws_sample, nnz_cap, s, ranks, A_dev, ws, ws_bytes, &P);
   if (rc != MACH_OK) return rc;
@@ -480,14 +482,14 @@ mach_status mach_hooi_sweep(const void* ws_sample, uint64_t nnz_cap, const mach_
   bool ok = launch_factors_to_f32(P.si, P.SL, w, A_dev, ranks, hdr, st) == hipSuccess;
   int tail0 = first_mode;
   if (first_mode < h) {
-    ok = ok && launch_contract_tail(P.si, P.sp, P.SL, w, ranks, density, st) == hipSuccess;
+    ok = ok && launch_contract_tail(P.si, P.sp, P.SL, w, ranks, density, bf16, st) == hipSuccess;
     for (int k = first_mode; k < h && ok; ++k) {
       ok = launch_form_y(P.si, P.SL, w, k, hdr, st) == hipSuccess;
       ok = ok && launch_mode_update(P.si, P.SL, w, k, A_dev[k], hdr, st) == hipSuccess;
     }
     tail0 = h;
   }
-  ok = ok && launch_contract_head(P.si, P.sp, P.SL, w, ranks, density, st) == hipSuccess;
+  ok = ok && launch_contract_head(P.si, P.sp, P.SL, w, ranks, density, bf16, st) == hipSuccess;
   for (int k = tail0; k < d && ok; ++k) {
     ok = launch_form_y(P.si, P.SL, w, k, hdr, st) == hipSuccess;
     ok = ok && launch_mode_update(P.si, P.SL, w, k, A_dev[k], hdr, st) == hipSuccess;
@@ -508,7 +510,7 @@ mach_status mach_core(const void* ws_sample, uint64_t nnz_cap, const mach_shape*
   const double density = (double)nnz_cap / (double)P.si.N;
   const SampleHdr* hdr = P.sp.hdr;
   bool ok = launch_factors_to_f32(P.si, P.SL, w, A_dev, ranks, hdr, st) == hipSuccess;
-  ok = ok && launch_contract_head(P.si, P.sp, P.SL, w, ranks, density, st) == hipSuccess;
+  ok = ok && launch_contract_head(P.si, P.sp, P.SL, w, ranks, density, 0, st) == hipSuccess;
   ok = ok && launch_form_y(P.si, P.SL, w, P.si.d - 1, hdr, st) == hipSuccess;
   ok = ok && launch_core(P.si, P.SL, w, A_dev[P.si.d - 1], G_dev, core_norm2_dev, hdr, st) ==
                  hipSuccess;

@@ -54,6 +54,7 @@ constexpr int kTagRR = 8, kTagCold = 9, kTagDone = 10;
 struct SolverLayout {
   size_t status;                         // see above
   size_t af[kMaxD];                      // float32 factors, I_k x 16
+  size_t af16[kMaxD];                    // bfloat16 copies for the mixed-precision sweep
   size_t TH, TT;
   size_t G, Gpart, Gpart_elems;          // float64 Gram and its partials
   size_t Aw;                             // float64 I_max x 16 scratch
@@ -88,9 +89,11 @@ SparsePtrs sparse_ptrs(const char* ws_sample, const SampleLayout& L);
 // Sparse passes (ttm.hip).  density = nnz_cap / N, used only to pick the
 // number of lanes per segment.
 hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
-                                char* ws, const int32_t* ranks, double density, hipStream_t st);
+                                char* ws, const int32_t* ranks, double density, int bf16,
+                                hipStream_t st);
 hipError_t launch_contract_head(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
-                                char* ws, const int32_t* ranks, double density, hipStream_t st);
+                                char* ws, const int32_t* ranks, double density, int bf16,
+                                hipStream_t st);
 hipError_t launch_form_y(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k,
                          const SampleHdr* hdr, hipStream_t st);
 hipError_t launch_factors_to_f32(const ShapeInfo& si, const SolverLayout& SL, char* ws,

@@ -29,8 +29,8 @@ struct SpcArgs {
   uint32_t MT;
   FastDiv fMT, flo;        // flo divides x into (hi, lo) contracted coordinates
   int inner_is_lo;
-  const float* Ain;        // inner factor, row stride 16, zero padded
-  const float* Aout;       // outer factor (two contracted modes only)
+  const void* Ain;         // inner factor, row stride 16, zero padded (float32 or bfloat16)
+  const void* Aout;        // outer factor (two contracted modes only)
   uint32_t Rin, Rout;
   float* out;              // out[seg * K + kappa]
   uint32_t K;
@@ -48,7 +48,20 @@ constexpr uint32_t kStage = 4096;
 // columns 4*quad .. 4*quad+3, so the LPE lanes gather one contiguous 16*LPE
 // byte factor row together (one cache line per entry instead of one per
 // lane and float4).  The G lanes of a segment form S = G / LPE entry slots.
-template <int NQ, int RI, int RO, int CSC>
+// Four factor entries (columns 4 quad .. 4 quad + 3 of a row) as float32,
+// from float32 or bfloat16 (BF) storage.
+template <int BF>
+__device__ __forceinline__ float4 factor4(const void* A, size_t row, int quad) {
+  if constexpr (BF) {
+    const uint2 u = reinterpret_cast<const uint2*>(A)[row * 4 + quad];
+    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                       __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+  } else {
+    return reinterpret_cast<const float4*>(A)[row * 4 + quad];
+  }
+}
+
+template <int NQ, int RI, int RO, int CSC, int BF>
 __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
   if (a.hdr->status != 0 || *a.st_solver != 0) return;
   constexpr int LPE = RI / 4;
@@ -80,8 +93,6 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
     lo = b0 + (uint32_t)(((uint64_t)L * slot) / S);
     hi = b0 + (uint32_t)(((uint64_t)L * (slot + 1)) / S);
   }
-  const float4* Ain4 = reinterpret_cast<const float4*>(a.Ain);
-  const float4* Aout4 = reinterpret_cast<const float4*>(a.Aout);
   constexpr int NS = (NQ == 2) ? RO * 4 : 4;
   float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
   float s[NS];
@@ -145,7 +156,7 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
           iin = a.inner_is_lo ? l : h;
           io[u] = ok ? (a.inner_is_lo ? h : l) : 0xffffffffu;
         }
-        w[u] = Ain4[(size_t)iin * 4 + quad];
+        w[u] = factor4<BF>(a.Ain, iin, quad);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -153,7 +164,7 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
           if (cur != 0xffffffffu) {
 #pragma unroll
             for (int o4 = 0; o4 < RO / 4; ++o4) {
-              const float4 wo = Aout4[(size_t)cur * 4 + o4];
+              const float4 wo = factor4<BF>(a.Aout, cur, o4);
               const float wv[4] = {wo.x, wo.y, wo.z, wo.w};
 #pragma unroll
               for (int oo = 0; oo < 4; ++oo) {
@@ -179,7 +190,7 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
     if (cur != 0xffffffffu) {
 #pragma unroll
       for (int o4 = 0; o4 < RO / 4; ++o4) {
-        const float4 wo = Aout4[(size_t)cur * 4 + o4];
+        const float4 wo = factor4<BF>(a.Aout, cur, o4);
         const float wv[4] = {wo.x, wo.y, wo.z, wo.w};
 #pragma unroll
         for (int oo = 0; oo < 4; ++oo) {
@@ -216,33 +227,33 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
 
 inline int pad4(uint32_t r) { return r <= 4 ? 4 : r <= 8 ? 8 : r <= 12 ? 12 : 16; }
 
-template <int NQ, int RI, int RO, int CSC>
+template <int NQ, int RI, int RO, int CSC, int BF>
 hipError_t go_c(const SpcArgs& a, hipStream_t st) {
   uint32_t per = 256u / a.G;
   dim3 grid((a.nseg + per - 1) / per);
   hipEvent_t e0, e1;
   if (timing_events(CSC, &e0, &e1))
-    hipExtLaunchKernelGGL((k_spc<NQ, RI, RO, CSC>), grid, dim3(256), 0, st, e0, e1, 0, a);
+    hipExtLaunchKernelGGL((k_spc<NQ, RI, RO, CSC, BF>), grid, dim3(256), 0, st, e0, e1, 0, a);
   else
-    hipLaunchKernelGGL((k_spc<NQ, RI, RO, CSC>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_spc<NQ, RI, RO, CSC, BF>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
-template <int NQ, int RI, int RO>
+template <int NQ, int RI, int RO, int BF>
 hipError_t go(const SpcArgs& a, hipStream_t st) {
-  return a.csc ? go_c<NQ, RI, RO, 1>(a, st) : go_c<NQ, RI, RO, 0>(a, st);
+  return a.csc ? go_c<NQ, RI, RO, 1, BF>(a, st) : go_c<NQ, RI, RO, 0, BF>(a, st);
 }
 
-template <int NQ, int RI>
+template <int NQ, int RI, int BF>
 hipError_t go_ro(const SpcArgs& a, hipStream_t st) {
   if constexpr (NQ == 1) {
-    return go<NQ, RI, 1>(a, st);
+    return go<NQ, RI, 1, BF>(a, st);
   } else {
     switch (pad4(a.Rout)) {
-      case 4: return go<NQ, RI, 4>(a, st);
-      case 8: return go<NQ, RI, 8>(a, st);
-      case 12: return go<NQ, RI, 12>(a, st);
-      default: return go<NQ, RI, 16>(a, st);
+      case 4: return go<NQ, RI, 4, BF>(a, st);
+      case 8: return go<NQ, RI, 8, BF>(a, st);
+      case 12: return go<NQ, RI, 12, BF>(a, st);
+      default: return go<NQ, RI, 16, BF>(a, st);
     }
   }
 }
@@ -251,15 +262,54 @@ hipError_t go_ro(const SpcArgs& a, hipStream_t st) {
 // of two; factor rows are zero-padded to 16 columns, so 12 reads as 16).
 inline int pad_inner(uint32_t r) { return r <= 4 ? 4 : r <= 8 ? 8 : 16; }
 
-template <int NQ>
+template <int NQ, int BF>
 hipError_t go_ri(SpcArgs a, hipStream_t st) {
   const int ri = pad_inner(a.Rin);
   a.G *= ri / 4;
   switch (ri) {
-    case 4: return go_ro<NQ, 4>(a, st);
-    case 8: return go_ro<NQ, 8>(a, st);
-    default: return go_ro<NQ, 16>(a, st);
+    case 4: return go_ro<NQ, 4, BF>(a, st);
+    case 8: return go_ro<NQ, 8, BF>(a, st);
+    default: return go_ro<NQ, 16, BF>(a, st);
   }
+}
+
+hipError_t go_any(const SpcArgs& a, int nq, int bf, hipStream_t st) {
+  if (bf) return nq == 2 ? go_ri<2, 1>(a, st) : go_ri<1, 1>(a, st);
+  return nq == 2 ? go_ri<2, 0>(a, st) : go_ri<1, 0>(a, st);
+}
+
+// bfloat16 copies (round to nearest even) of the float32 factor copies of
+// the listed modes, for the mixed-precision sparse passes.
+struct Bf16Args {
+  const float* src[kMaxD];
+  uint16_t* dst[kMaxD];
+  uint32_t n[kMaxD];      // elements (I_k x 16)
+  int count;
+};
+
+__global__ void k_factors_to_bf16(Bf16Args a, const SampleHdr* hdr) {
+  if (hdr->status != 0) return;
+  const int k = blockIdx.y;
+  if (k >= a.count) return;
+  const uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.n[k]) return;
+  const uint32_t u = __float_as_uint(a.src[k][e]);
+  a.dst[k][e] = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+hipError_t to_bf16(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k0, int k1,
+                   const SampleHdr* hdr, hipStream_t st) {
+  Bf16Args b{};
+  uint32_t nmax = 1;
+  for (int k = k0; k < k1; ++k) {
+    b.src[b.count] = (const float*)(ws + SL.af[k]);
+    b.dst[b.count] = (uint16_t*)(ws + SL.af16[k]);
+    b.n[b.count] = si.dims[k] * 16;
+    if (b.n[b.count] > nmax) nmax = b.n[b.count];
+    ++b.count;
+  }
+  hipLaunchKernelGGL(k_factors_to_bf16, dim3((nmax + 255) / 256, b.count), dim3(256), 0, st, b, hdr);
+  return hipGetLastError();
 }
 
 // Entry slots per segment: a power of two, at most 16, with an expected
@@ -323,7 +373,13 @@ __global__ void k_factors_to_f32(F32Args a, const SampleHdr* hdr) {
 }  // namespace
 
 hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
-                                char* ws, const int32_t* ranks, double density, hipStream_t st) {
+                                char* ws, const int32_t* ranks, double density, int bf16,
+                                hipStream_t st) {
+  if (bf16) {
+    hipError_t e = to_bf16(si, SL, ws, si.h, si.d, sp.hdr, st);
+    if (e != hipSuccess) return e;
+  }
+  const size_t* fac = bf16 ? SL.af16 : SL.af;
   SpcArgs a{};
   a.ent = sp.coo_l;
   a.segptr = sp.rowptr;
@@ -332,12 +388,12 @@ hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const
   a.MT = si.MT;
   a.fMT = si.fMT;
   int q = si.d - si.h;
-  a.Ain = (const float*)(ws + SL.af[si.d - 1]);
+  a.Ain = (const void*)(ws + fac[si.d - 1]);
   a.Rin = ranks[si.d - 1];
   if (q == 2) {
     a.flo = si.fdim[si.d - 1];
     a.inner_is_lo = 1;
-    a.Aout = (const float*)(ws + SL.af[si.h]);
+    a.Aout = (const void*)(ws + fac[si.h]);
     a.Rout = ranks[si.h];
   } else {
     a.flo = make_fastdiv(1);
@@ -349,11 +405,17 @@ hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const
   a.G = slots_per_segment(density, si.MT);
   a.hdr = sp.hdr;
   a.st_solver = (const int32_t*)(ws + SL.status);
-  return q == 2 ? go_ri<2>(a, st) : go_ri<1>(a, st);
+  return go_any(a, q, bf16, st);
 }
 
 hipError_t launch_contract_head(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
-                                char* ws, const int32_t* ranks, double density, hipStream_t st) {
+                                char* ws, const int32_t* ranks, double density, int bf16,
+                                hipStream_t st) {
+  if (bf16) {
+    hipError_t e = to_bf16(si, SL, ws, 0, si.h, sp.hdr, st);
+    if (e != hipSuccess) return e;
+  }
+  const size_t* fac = bf16 ? SL.af16 : SL.af;
   SpcArgs a{};
   a.ent = sp.coo_t;
   a.segptr = sp.colptr;
@@ -366,13 +428,13 @@ hipError_t launch_contract_head(const ShapeInfo& si, const SparsePtrs& sp, const
     int inner = si.headperm[1], outer = si.headperm[0];
     a.flo = si.fdim[1];
     a.inner_is_lo = inner == 1;
-    a.Ain = (const float*)(ws + SL.af[inner]);
+    a.Ain = (const void*)(ws + fac[inner]);
     a.Rin = ranks[inner];
-    a.Aout = (const float*)(ws + SL.af[outer]);
+    a.Aout = (const void*)(ws + fac[outer]);
     a.Rout = ranks[outer];
   } else {
     a.flo = make_fastdiv(1);
-    a.Ain = (const float*)(ws + SL.af[0]);
+    a.Ain = (const void*)(ws + fac[0]);
     a.Rin = ranks[0];
       a.Aout = a.Ain;
     a.Rout = 1;
@@ -382,7 +444,7 @@ hipError_t launch_contract_head(const ShapeInfo& si, const SparsePtrs& sp, const
   a.G = slots_per_segment(density, si.MH);
   a.hdr = sp.hdr;
   a.st_solver = (const int32_t*)(ws + SL.status);
-  return q == 2 ? go_ri<2>(a, st) : go_ri<1>(a, st);
+  return go_any(a, q, bf16, st);
 }
 
 hipError_t launch_form_y(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k,
