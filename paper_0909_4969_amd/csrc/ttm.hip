@@ -34,7 +34,9 @@ struct SpcArgs {
   uint32_t Rin, Rout;
   float* out;              // out[seg * K + kappa]
   uint32_t K;
-  int G;                   // lanes per segment (power of two, 1..64)
+  int G;                   // lanes per segment (power of two, 1..256)
+  double density;          // expected kept fraction, and the dense length of a segment
+  uint32_t dense_len;
   const SampleHdr* hdr;
   const int32_t* st_solver;
 };
@@ -69,8 +71,7 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
   __shared__ uint64_t stage[kStage];
   const int G = a.G;
   const int S = G / LPE;
-  const int lane = threadIdx.x & 63;
-  const int gl = lane & (G - 1);
+  const int gl = threadIdx.x & (G - 1);
   const int quad = gl & (LPE - 1);
   const int slot = gl / LPE;
   const uint32_t per = 256u / G;
@@ -208,10 +209,24 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
     s[2] = t.z;
     s[3] = t.w;
   }
-  // Sum the S slots of the segment (fixed butterfly order).
-  for (int m = LPE; m < G; m <<= 1) {
+  // Sum the S slots of the segment: a fixed xor butterfly within each wave,
+  // then (segments wider than a wave) the wave sums in wave order via LDS.
+  const int GW = G < 64 ? G : 64;
+  for (int m = LPE; m < GW; m <<= 1) {
 #pragma unroll
     for (int j = 0; j < NS; ++j) s[j] += __shfl_xor(s[j], m, 64);
+  }
+  if (G > 64) {
+    __shared__ float red[4][4][NS];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < LPE)
+#pragma unroll
+      for (int j = 0; j < NS; ++j) red[wv][quad][j] = s[j];
+    __syncthreads();
+    if (gl < LPE)
+      for (int w2 = 1; w2 < G / 64; ++w2)
+#pragma unroll
+        for (int j = 0; j < NS; ++j) s[j] += red[wv + w2][quad][j];
   }
   if (!valid || slot != 0) return;
   float* o = a.out + (size_t)seg * a.K;
@@ -262,10 +277,23 @@ hipError_t go_ro(const SpcArgs& a, hipStream_t st) {
 // of two; factor rows are zero-padded to 16 columns, so 12 reads as 16).
 inline int pad_inner(uint32_t r) { return r <= 4 ? 4 : r <= 8 ? 8 : 16; }
 
+// Entry slots per segment: a power of two with an expected kSlotEntries
+// entries or more per slot, such that the lanes per segment (slots times
+// the lanes per entry, lpe) stay within kMaxSegLanes (a segment may span up
+// to the four waves of a workgroup; one wave measured best on these passes).
+constexpr double kSlotEntries = 16.0;
+constexpr int kMaxSegLanes = 64;
+int slots_per_segment(double density, uint32_t dense_len, int lpe) {
+  double est = density * (double)dense_len;
+  int S = 1;
+  while (2 * S * lpe <= kMaxSegLanes && (double)(2 * S) * kSlotEntries <= est) S *= 2;
+  return S;
+}
+
 template <int NQ, int BF>
 hipError_t go_ri(SpcArgs a, hipStream_t st) {
   const int ri = pad_inner(a.Rin);
-  a.G *= ri / 4;
+  a.G = slots_per_segment(a.density, a.dense_len, ri / 4) * (ri / 4);
   switch (ri) {
     case 4: return go_ro<NQ, 4, BF>(a, st);
     case 8: return go_ro<NQ, 8, BF>(a, st);
@@ -312,15 +340,6 @@ hipError_t to_bf16(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k0
   return hipGetLastError();
 }
 
-// Entry slots per segment: a power of two, at most 16, with an expected
-// eight entries or more per slot.  The lanes per segment are this times the
-// lanes per entry (at most 4), so at most 64.
-int slots_per_segment(double density, uint32_t dense_len) {
-  double est = density * (double)dense_len;
-  int S = 1;
-  while (S < 16 && (double)(2 * S) * 8.0 <= est) S *= 2;
-  return S;
-}
 
 // out[(o*R + r)*Q + q] = sum_i A[i*16 + r] * in[(o*I + i)*Q + q].  A
 // workgroup owns 64 consecutive outputs; its 4 waves take every 4th i with
@@ -402,7 +421,8 @@ hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const
   }
   a.out = (float*)(ws + SL.TH);
   a.K = SL.KT;
-  a.G = slots_per_segment(density, si.MT);
+  a.density = density;
+  a.dense_len = si.MT;
   a.hdr = sp.hdr;
   a.st_solver = (const int32_t*)(ws + SL.status);
   return go_any(a, q, bf16, st);
@@ -441,7 +461,8 @@ hipError_t launch_contract_head(const ShapeInfo& si, const SparsePtrs& sp, const
   }
   a.out = (float*)(ws + SL.TT);
   a.K = SL.KH;
-  a.G = slots_per_segment(density, si.MH);
+  a.density = density;
+  a.dense_len = si.MH;
   a.hdr = sp.hdr;
   a.st_solver = (const int32_t*)(ws + SL.status);
   return go_any(a, q, bf16, st);
