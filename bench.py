@@ -49,7 +49,8 @@ def parse():
                     help="windows of the serving run (0: skip it)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (the "
-                         "reference kernel for scaling HBM counters)")
+                         "reference kernel for scaling HBM counters; larger than the 256 MB "
+                         "last-level cache, so that it streams from HBM)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the TTM traffic summary from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this script with --copy-mib, and exit")
@@ -76,9 +77,9 @@ def pmc_summary(fetch_dir, write_dir, copy_mib):
         acc = {}
         for r in rows:
             n = r["Kernel_Name"]
-            m = re.search(r"k_spc<(\d), (\d+), (\d+), (\d)>", n)
+            m = re.search(r"k_spc<(\d), (\d+), (\d+), (\d), (\d)>", n)
             key = None
-            if m:
+            if m and m.group(5) == "0":      # float32 factors (the timed path)
                 key = "ttm_tail_cols" if m.group(4) == "1" else "ttm_head_rows"
             elif "copyBuffer" in n and int(r["Grid_Size"]) == big:
                 key = "copy"
@@ -100,9 +101,9 @@ def pmc_summary(fetch_dir, write_dir, copy_mib):
            "commands": [
                "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE "
                "--output-format csv -d $R/gpurun_out/pmc_fetch -o run -- python3 $R/bench.py --steps 1 "
-               "--warmup 1 --no-cpu-baseline --serve-requests 0 --copy-mib 256",
+               "--warmup 1 --no-cpu-baseline --serve-requests 0 --copy-mib 1024",
                "(the same with --pmc WRITE_SIZE and -d $R/gpurun_out/pmc_write)",
-               "python3 bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write --copy-mib 256"]}
+               "python3 bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write --copy-mib 1024"]}
     return out
 
 

@@ -20,6 +20,8 @@
 // (lowest row on ties).
 #include <cmath>
 
+#include <algorithm>
+
 #include "solver.h"
 
 namespace mach {
@@ -398,7 +400,22 @@ __global__ __launch_bounds__(NT) void k_jacobi_small(JacArgs a) {
 // factor subspaces moved; Newton-Schulz steps restore orthogonality.
 // part[(slot * 256 + a * 16 + b) * kCtcChunks + chunk] = sum over the chunk's
 // rows i of old[i][a] * cur[i][b] (float32 factors I_j x 16, float64 sums).
-constexpr uint32_t kCtcChunks = 128;
+constexpr uint32_t kCtcChunks = 64;
+
+// Copies of the other modes' float32 factors, taken after a column-side solve.
+struct SnapArgs {
+  const float4* src[3];
+  float4* dst[3];
+  uint32_t n4[3];
+  int n;
+};
+
+__global__ void k_snapshot(SnapArgs a, Status s) {
+  if (s.skip()) return;
+  const int j = blockIdx.y;
+  const uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (j < a.n && e < a.n4[j]) a.dst[j][e] = a.src[j][e];
+}
 
 struct CtcArgs {
   const float* old[3];
@@ -409,22 +426,37 @@ struct CtcArgs {
 };
 
 __host__ __device__ inline uint32_t ctc_chunks(uint32_t I) {
-  uint32_t c = (I + 127) / 128;
+  uint32_t c = (I + 255) / 256;
   return c < 1 ? 1 : (c > kCtcChunks ? kCtcChunks : c);
 }
 
+// Rows are staged through LDS 256 at a time (coalesced float4 loads), then
+// thread (a, b) sums old[i][a] * cur[i][b] over them.
 __global__ __launch_bounds__(256) void k_ctc_partial(CtcArgs a, double* __restrict__ part, Status s) {
   if (s.skip()) return;
   const int slot = blockIdx.y;
   if (slot >= a.n || blockIdx.x >= a.nch[slot]) return;
+  __shared__ float so[256][17];
+  __shared__ float sc[256][17];
   const uint32_t I = a.I[slot];
   const uint32_t rows = (I + a.nch[slot] - 1) / a.nch[slot];
   const uint32_t i0 = blockIdx.x * rows, i1 = min(I, i0 + rows);
   const int aa = threadIdx.x >> 4, bb = threadIdx.x & 15;
-  const float* po = a.old[slot];
-  const float* pc = a.cur[slot];
+  const float4* po = reinterpret_cast<const float4*>(a.old[slot]);
+  const float4* pc = reinterpret_cast<const float4*>(a.cur[slot]);
   double acc = 0.0;
-  for (uint32_t i = i0; i < i1; ++i) acc = fma((double)po[(size_t)i * 16 + aa], (double)pc[(size_t)i * 16 + bb], acc);
+  for (uint32_t b0 = i0; b0 < i1; b0 += 256) {
+    const uint32_t nb = min(256u, i1 - b0);
+    for (uint32_t e = threadIdx.x; e < nb * 4; e += 256) {
+      const float4 vo = po[(size_t)b0 * 4 + e], vc = pc[(size_t)b0 * 4 + e];
+      const uint32_t r = e >> 2, c = (e & 3) * 4;
+      so[r][c] = vo.x; so[r][c + 1] = vo.y; so[r][c + 2] = vo.z; so[r][c + 3] = vo.w;
+      sc[r][c] = vc.x; sc[r][c + 1] = vc.y; sc[r][c + 2] = vc.z; sc[r][c + 3] = vc.w;
+    }
+    __syncthreads();
+    for (uint32_t r = 0; r < nb; ++r) acc = fma((double)so[r][aa], (double)sc[r][bb], acc);
+    __syncthreads();
+  }
   part[((size_t)slot * 256 + threadIdx.x) * kCtcChunks + blockIdx.x] = acc;   // chunks < nch[slot] used
 }
 
@@ -1526,12 +1558,17 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     else
       hipLaunchKernelGGL((k_mode_solve<64, 1024>), dim3(1), dim3(1024), 0, st, a);
     if (m.kside) {
+      SnapArgs sa{};
+      uint32_t nmax = 1;
       for (int j = 0; j < si.d; ++j) {
         if (j == k) continue;
-        e = hipMemcpyAsync(ws + m.snap[j], ws + SL.af[j], (size_t)si.dims[j] * 16 * 4,
-                           hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return e;
+        sa.src[sa.n] = (const float4*)(ws + SL.af[j]);
+        sa.dst[sa.n] = (float4*)(ws + m.snap[j]);
+        sa.n4[sa.n] = si.dims[j] * 4;
+        nmax = std::max(nmax, sa.n4[sa.n]);
+        ++sa.n;
       }
+      hipLaunchKernelGGL(k_snapshot, dim3(cdiv(nmax, 256), sa.n), dim3(256), 0, st, sa, c.stat());
       uint32_t nwg = cdiv(m.I, 256);
       double* part = c.d(SL.part);
       hipLaunchKernelGGL(k_bp_tall, dim3(nwg), dim3(256), 0, st, (const float*)(ws + m.ybuf), m.O, m.I,
