@@ -45,21 +45,9 @@ constexpr int kMaxSweeps = 40;
 // about 1e-7, so a tighter test would only resolve rounding noise.
 constexpr double kOffTol2 = 1e-16;
 
-__device__ __forceinline__ void jpair(int r, int k, int np, int* p, int* q) {
-  int m = np - 1, a, b;
-  if (k == 0) {
-    a = r;
-    b = m;
-  } else {
-    a = (r + k) % m;
-    b = (r - k + m) % m;
-  }
-  *p = a < b ? a : b;
-  *q = a < b ? b : a;
-}
-
-// The same pairing with the size a compile-time constant (the modulo by
-// NP - 1 becomes a multiply and shift), for the per-round index math.
+// Round-robin pairing of NP indices (NP even): in round r < NP - 1, pair k
+// joins (r + k) mod (NP - 1) and (r - k) mod (NP - 1), and pair 0 joins r
+// and NP - 1; every pair of indices meets exactly once per sweep.
 template <int NP>
 __device__ __forceinline__ void jpair_c(int r, int k, int* p, int* q) {
   constexpr int m = NP - 1;
@@ -118,7 +106,6 @@ struct JacLds {
   double V[NP][NP + 1];                 // accumulated rotations
   double W[NP][NP + 1];                 // scratch (warm-start products)
   double rc[NP / 2], rs[NP / 2], rt[NP / 2];
-  unsigned char tp[NP - 1][NP / 2], tq[NP - 1][NP / 2];
   int rk[NP];
   double red[2][16];
 };
@@ -194,12 +181,6 @@ __device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin,
       L.V[x][y] = (warm && x < n && y < n) ? Vin[x * n + y] : (x == y ? 1.0 : 0.0);
     }
   warm = warm || in_lds;
-  for (int e = tid; e < (NP - 1) * (NP / 2); e += NT) {
-    int r = e / (NP / 2), k = e % (NP / 2), p, q;
-    jpair(r, k, NP, &p, &q);
-    L.tp[r][k] = (unsigned char)p;
-    L.tq[r][k] = (unsigned char)q;
-  }
   __syncthreads();
   if (!warm) return;
   // W = G V, then A = V^T W; 4x4 register blocks per thread.
