@@ -100,6 +100,35 @@ struct JacArgs {
 };
 
 // LDS state of the Jacobi kernels for a padded size NP (power of two).
+// Broadcast of a float64 register from lane `src` (wave-uniform) to the wave.
+__device__ inline double lane_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Right-looking Cholesky of a 16 x 16 symmetric positive definite block held
+// by rows in registers: lane x < 16 passes row x in a[], and gets back row x
+// of L (zeros above the diagonal).  Only entries on and below the diagonal
+// are read; a pivot below 1e-300 is replaced by 1 (degenerate input stays
+// finite; the eigenvalue test reports it).  Every lane of the wave calls it:
+// the column of L is broadcast from lanes 0..15 with readlane.
+__device__ inline void chol16_wave(double (&a)[16], int x) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double d = lane_bcast(a[j], j);
+    const double sd = d > 1e-300 ? sqrt(d) : 1.0;
+    const double l = x == j ? sd : a[j] / sd;
+    a[j] = l;
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k) a[k] = fma(-l, lane_bcast(l, k), a[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (k > x) a[k] = 0.0;
+}
+
 template <int NP>
 struct JacLds {
   double A[NP][NP + 1];                 // the matrix being diagonalised
@@ -631,48 +660,37 @@ __global__ __launch_bounds__(256) void k_bp_tall(const float* __restrict__ Y, ui
 }
 
 // One Cholesky-QR pass on Aw (I x 16): every workgroup sums the Gram
-// partials (fixed order), factors S = L L^T in one wave, and replaces its
-// rows by a L^{-T}; then writes per-workgroup column maxima of |a| for the
-// sign rule.
+// partials (fixed order), factors S = L L^T in one wave (registers), and
+// replaces each of its rows a by the solution q of q L^T = a; then writes
+// per-workgroup column maxima of |q| for the sign rule.
 __global__ __launch_bounds__(256) void k_chol_apply_tall(double* __restrict__ Aw, uint32_t I, uint32_t R,
                                                          const double* __restrict__ part, uint32_t nchunk,
                                                          double* __restrict__ pv, uint32_t* __restrict__ pi,
                                                          Status s) {
   if (s.skip()) return;
   __shared__ double S[16][17];
-  __shared__ double Li[16][17];
+  __shared__ double rinv[16];
   __shared__ double bv[256];
   __shared__ uint32_t bi[256];
   const int tid = threadIdx.x;
   {
     double g = 0.0;
     for (uint32_t c = 0; c < nchunk; ++c) g += part[(size_t)c * 256 + tid];
-    S[tid >> 4][tid & 15] = g;
+    const int x = tid >> 4, y = tid & 15;
+    // columns at or beyond R are zero: factor the identity there
+    S[x][y] = (x < (int)R && y < (int)R) ? g : (x == y ? 1.0 : 0.0);
   }
   __syncthreads();
   if (tid < 64) {
-    // lane x owns row x of S; right-looking Cholesky, then L^{-1} by
-    // forward substitution (column j of L^{-1} in lane j).
     const int x = tid;
-    for (uint32_t j = 0; j < R; ++j) {
-      if (x == (int)j) S[j][j] = sqrt(fmax(S[j][j], 1e-300));
-      __builtin_amdgcn_wave_barrier();
-      double d = S[j][j];
-      if (x > (int)j && x < (int)R) S[x][j] /= d;
-      __builtin_amdgcn_wave_barrier();
-      if (x > (int)j && x < (int)R)
-        for (uint32_t k = j + 1; k <= (uint32_t)x; ++k) S[x][k] -= S[x][j] * S[k][j];
-      __builtin_amdgcn_wave_barrier();
-    }
-    if (x < 16)
-      for (int i = 0; i < 16; ++i) Li[i][x] = 0.0;
-    __builtin_amdgcn_wave_barrier();
-    if (x < (int)R) {
-      for (uint32_t i = x; i < R; ++i) {
-        double v = (i == (uint32_t)x) ? 1.0 : 0.0;
-        for (uint32_t k = x; k < i; ++k) v -= S[i][k] * Li[k][x];
-        Li[i][x] = v / S[i][i];
-      }
+    double a[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a[k] = x < 16 ? S[x][k] : 0.0;
+    chol16_wave(a, x);
+    if (x < 16) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) S[x][k] = a[k];
+      rinv[x] = 1.0 / a[x];
     }
   }
   __syncthreads();
@@ -684,13 +702,13 @@ __global__ __launch_bounds__(256) void k_chol_apply_tall(double* __restrict__ Aw
     double a[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) a[r] = Aw[(size_t)i * 16 + r];
-    // a L^{-T}: out_j = sum_{k <= j} a_k Linv[j][k]
+    // forward substitution: out_j = (a_j - sum_{k < j} out_k L[j][k]) / L[j][j]
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      double v = 0.0;
+      double v = a[j];
 #pragma unroll
-      for (int k = 0; k <= j; ++k) v = fma(a[k], Li[j][k], v);
-      out[j] = (uint32_t)j < R ? v : 0.0;
+      for (int k = 0; k < j; ++k) v = fma(-out[k], S[j][k], v);
+      out[j] = (uint32_t)j < R ? v * rinv[j] : 0.0;
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) Aw[(size_t)i * 16 + r] = out[r];
@@ -893,25 +911,23 @@ __global__ void k_splitk_reduce(const double* __restrict__ P, uint32_t nks, uint
   C[(size_t)(e >> 6) * ldc + (e & 63)] = acc;
 }
 
-// B = L^{-T} for the Cholesky factor L of S + shift * tr(S) / n * I, with S
-// the sum of nchunk partials (chunk-minor, fixed order), n <= 64, so that
-// X B has orthonormal columns when S = X^T X.  The elimination runs on the
-// unscaled Schur complements, A[x][k] -= A[x][j] A[k][j] / A[j][j] for
-// j < k <= x, with the column A[.][j] copied out first so that each batch of
-// trailing entries is read before any is written; afterwards L[x][j] =
-// A[x][j] / sqrt(A[j][j]).  Wave 0 then forms L^{-1} (lane x: column x) by
-// forward substitution.
+// Cholesky-QR helper for an n x n Gram (n <= 64) summed from its chunk-minor
+// partials, with shift * trace / n added to the diagonal: S = L L^T and
+// B = L^{-T} (row-major n x n), both by 16 x 16 blocks.  A diagonal block is
+// factored by one wave in registers; panel solves and trailing updates use
+// all 256 threads; the inverse takes the diagonal blocks first (one wave
+// each) and then one block row at a time.  Indices at or beyond n are padded
+// with the identity.
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ part, uint32_t nchunk,
                                                   uint32_t n, double shift, double* __restrict__ B,
                                                   Status s) {
   if (s.skip()) return;
-  __shared__ double A[64][65];
-  __shared__ double Lm[64][65];
-  __shared__ double Li[64][65];
-  __shared__ double cj[64];
+  __shared__ double A[64][65];    // S, factored in place into L (upper part zero)
+  __shared__ double Li[64][65];   // L^{-1}
+  __shared__ double T[64][65];    // block-row products
   __shared__ double trs;
-  const int tid = threadIdx.x, x = tid & 63;
-  const int nn = (int)n;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nn = (int)n, nb = (nn + 15) / 16, E = nb * 16;
   for (int e = tid; e < 64 * 64; e += 256) {
     const int r = e >> 6, c = e & 63;
     double v = (r == c) ? 1.0 : 0.0;
@@ -922,66 +938,91 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ par
       for (uint32_t ch = 0; ch < nchunk; ++ch) v += p[ch];
     }
     A[r][c] = v;
+    Li[r][c] = 0.0;
   }
   __syncthreads();
   if (tid < 64) {
-    double tr = x < nn ? A[x][x] : 0.0;
+    double tr = lane < nn ? A[lane][lane] : 0.0;
     for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
-    if (x == 0) trs = tr;
+    if (lane == 0) trs = tr;
   }
   __syncthreads();
   if (tid < nn) A[tid][tid] += shift * trs / n;
   __syncthreads();
-  for (int j = 0; j < nn; ++j) {
-    const double dj = A[j][j];
-    const double ip = 1.0 / (dj > 1e-300 ? dj : 1.0);
-    if (tid < 64) cj[x] = x < nn ? A[x][j] : 0.0;
-    __syncthreads();
-    const int m = nn - j - 1, mm = m * m;
-    for (int base = 0; base < mm; base += 256 * 4) {
-      double val[4];
-      int xs[4], ks[4];
-      bool act[4];
+  for (int K = 0; K < nb; ++K) {
+    const int k0 = K * 16, m = E - k0 - 16;
+    if (w == 0) {
+      double a[16];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int e = base + tid + 256 * t;
-        const bool in = e < mm;
-        const int q = in ? e / m : 0;
-        xs[t] = j + 1 + q;                      // in [j + 1, nn) whenever in
-        ks[t] = in ? j + 1 + (e - q * m) : xs[t];
-        act[t] = in && ks[t] <= xs[t];
-        val[t] = A[in ? xs[t] : 0][in ? ks[t] : 0];
+      for (int k = 0; k < 16; ++k) a[k] = lane < 16 ? A[k0 + lane][k0 + k] : 0.0;
+      chol16_wave(a, lane);
+      if (lane < 16)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) A[k0 + lane][k0 + k] = a[k];
+    }
+    __syncthreads();
+    if (tid < m) {   // panel row r: solve l L_KK^T = A[r][k0 : k0 + 16]
+      const int r = k0 + 16 + tid;
+      double q[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        double v = A[r][k0 + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v = fma(-q[k], A[k0 + j][k0 + k], v);
+        q[j] = v / A[k0 + j][k0 + j];
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (act[t]) A[xs[t]][ks[t]] = val[t] - cj[xs[t]] * cj[ks[t]] * ip;
+      for (int j = 0; j < 16; ++j) {
+        A[r][k0 + j] = q[j];
+        A[k0 + j][r] = 0.0;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += 256) {   // trailing lower part -= panel panel^T
+      const int x = k0 + 16 + e / m, y = k0 + 16 + e % m;
+      if (y <= x) {
+        double v = A[x][y];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v = fma(-A[x][k0 + k], A[y][k0 + k], v);
+        A[x][y] = v;
+      }
     }
     __syncthreads();
   }
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    double v = (r == c) ? 1.0 : 0.0;
-    if (r < nn && c <= r) {
-      const double dc = A[c][c];
-      const double sc = dc > 1e-300 ? sqrt(dc) : 1.0;
-      v = (c == r) ? sc : A[r][c] / sc;
+  if (w < nb && lane < 16) {   // inverse of diagonal block w: column `lane`
+    const int k0 = w * 16;
+    double z[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double v = i == lane ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) v = fma(-A[k0 + i][k0 + k], z[k], v);
+      z[i] = v / A[k0 + i][k0 + i];
     }
-    Lm[r][c] = v;
-    Li[r][c] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Li[k0 + i][k0 + lane] = z[i];
   }
   __syncthreads();
-  if (tid >= 64) return;
-  for (int i = 0; i < nn; ++i) {
-    if (x <= i) {
-      double v = (i == x) ? 1.0 : 0.0;
-      for (int k = x; k < i; ++k) v -= Lm[i][k] * Li[k][x];
-      Li[i][x] = v / Lm[i][i];
+  for (int Ib = 1; Ib < nb; ++Ib) {
+    // T = sum_{J <= K < Ib} L[Ib][K] Li[K][J], then Li[Ib][J] = -Li[Ib][Ib] T
+    for (int e = tid; e < Ib * 256; e += 256) {
+      const int J = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      double v = 0.0;
+      for (int k = J * 16; k < Ib * 16; ++k) v = fma(A[Ib * 16 + r][k], Li[k][J * 16 + c], v);
+      T[Ib * 16 + r][J * 16 + c] = v;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
+    for (int e = tid; e < Ib * 256; e += 256) {
+      const int J = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v = fma(-Li[Ib * 16 + r][Ib * 16 + k], T[Ib * 16 + k][J * 16 + c], v);
+      Li[Ib * 16 + r][J * 16 + c] = v;
+    }
+    __syncthreads();
   }
   // B[k][j] = Li[j][k]
-  for (int e = x; e < nn * nn; e += 64) {
+  for (int e = tid; e < nn * nn; e += 256) {
     const int k = e / nn, j = e % nn;
     B[e] = Li[j][k];
   }
@@ -1202,12 +1243,33 @@ __global__ __launch_bounds__(256) void k_sign_store(const double* __restrict__ A
                                                     Status s) {
   if (s.skip()) return;
   __shared__ double sg[16];
+  __shared__ double bv[256];
+  __shared__ uint32_t bi[256];
+  {
+    // column r = tid % 16: 16 threads scan the chunk maxima, then one
+    // combines them (largest value, lowest row on ties: order-free)
+    const uint32_t r = threadIdx.x & 15, g = threadIdx.x >> 4;
+    double b = -1.0;
+    uint32_t bx = 0xffffffffu;
+#pragma unroll 4
+    for (uint32_t c = g; c < nchunk; c += 16) {
+      const double v = pv[c * 16 + r];
+      const uint32_t ix = pi[c * 16 + r];
+      if (v > b || (v == b && ix < bx)) {
+        b = v;
+        bx = ix;
+      }
+    }
+    bv[threadIdx.x] = b;
+    bi[threadIdx.x] = bx;
+  }
+  __syncthreads();
   if (threadIdx.x < 16) {
     double b = -1.0;
     uint32_t bx = 0xffffffffu;
-    for (uint32_t c = 0; c < nchunk; ++c) {
-      double v = pv[c * 16 + threadIdx.x];
-      uint32_t ix = pi[c * 16 + threadIdx.x];
+    for (int g = 0; g < 16; ++g) {
+      const double v = bv[g * 16 + threadIdx.x];
+      const uint32_t ix = bi[g * 16 + threadIdx.x];
       if (v > b || (v == b && ix < bx)) {
         b = v;
         bx = ix;
