@@ -4,6 +4,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "mach_internal.h"
@@ -278,26 +279,6 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
       }
     }
   }
-  // Column strides of the other modes in Y_(k): C order over the head modes
-  // (KH) and over the tail modes (KT); a contracted second mode of the own
-  // side comes first, with stride KT (head side) or KH (tail side).
-  {
-    uint32_t stH[kMaxD] = {}, stT[kMaxD] = {};
-    uint32_t acc = 1;
-    for (int j = h - 1; j >= 0; --j) { stH[j] = acc; acc *= R(j); }
-    acc = 1;
-    for (int j = d - 1; j >= h; --j) { stT[j] = acc; acc *= R(j); }
-    for (int k = 0; k < d; ++k) {
-      ModePlan& m = S.mp[k];
-      const bool head = k < h;
-      for (int j = 0; j < d; ++j) {
-        if (j == k) continue;
-        const bool jhead = j < h;
-        if (jhead == head) m.kst[j] = head ? S.KT : S.KH;   // the contracted partner
-        else m.kst[j] = jhead ? stH[j] : stT[j];
-      }
-    }
-  }
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -349,9 +330,26 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   S.skpart = take(skmax * 8);
   S.pv = take(1024 * 16 * 8);
   S.pi = take(1024 * 16 * 4);
+  S.tags = S.status + 16;
+  if (d >= 2) {   // second scratch copy for the last mode's HOSVD
+    const size_t sz[16] = {gmax * 8, S.Gpart_elems * 8, (size_t)imax * 16 * 8,
+                           (size_t)zrows * kBlock * 8, (size_t)zrows * kBlock * 8,
+                           (size_t)zrows * kBlock * 8, (size_t)zrows * kBlock * 8, 64 * 64 * 8,
+                           64 * 64 * 8, 64 * 64 * 8, 64 * 8, 64 * 64 * 64 * 8, skmax * 8,
+                           1024 * 16 * 8, 1024 * 16 * 4, 256};
+    for (int f = 0; f < 16; ++f) S.laneb[f] = take(sz[f]);
+  }
   S.total = o;
   *out = S;
   return true;
+}
+
+SolverLayout solver_lane_b(const SolverLayout& S) {
+  SolverLayout B = S;
+  size_t* f[16] = {&B.G, &B.Gpart, &B.Aw, &B.Zs, &B.Z2s, &B.Qrs, &B.Qhs, &B.H,
+                   &B.VH, &B.small, &B.lamH, &B.part, &B.skpart, &B.pv, &B.pi, &B.tags};
+  for (int i = 0; i < 16; ++i) *f[i] = S.laneb[i];
+  return B;
 }
 
 SparsePtrs sparse_ptrs(const char* ws, const SampleLayout& L) {
@@ -426,6 +424,42 @@ mach_status prepare(const void* ws_sample, uint64_t cap, const mach_shape* s, co
 }  // namespace
 }  // namespace mach
 
+namespace {
+
+// Auxiliary stream and fork/join events per (device, caller stream),
+// created on first use and kept for the life of the process.  Streams are
+// non-blocking at the default priority.
+struct AuxLane {
+  int dev;
+  hipStream_t caller, st;
+  hipEvent_t fork, join;
+};
+std::mutex g_aux_mu;
+std::vector<AuxLane*> g_aux;
+
+AuxLane* aux_lane(hipStream_t caller) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  for (AuxLane* a : g_aux)
+    if (a->dev == dev && a->caller == caller) return a;
+  AuxLane* a = new AuxLane{dev, caller, nullptr, nullptr, nullptr};
+  if (hipStreamCreateWithFlags(&a->st, hipStreamNonBlocking) != hipSuccess) {
+    delete a;
+    return nullptr;
+  }
+  if (hipEventCreateWithFlags(&a->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&a->join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(a->st);
+    delete a;
+    return nullptr;
+  }
+  g_aux.push_back(a);
+  return a;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t mach_solver_workspace_bytes(const mach_shape* s, const int32_t* ranks, mach_dtype prec,
@@ -458,9 +492,24 @@ mach_status mach_hosvd(const void* ws_sample, uint64_t nnz_cap, const mach_shape
   hipStream_t st = (hipStream_t)stream;
   char* w = (char*)ws;
   if (launch_solver_init(P.SL, w, st) != hipSuccess) return MACH_EDEVICE;
-  for (int n = 0; n < P.si.d; ++n)
+  const int d = P.si.d;
+  // The modes' HOSVDs are independent: the last one (usually the largest
+  // Gram) runs on an auxiliary stream with its own scratch, forked from and
+  // joined back into `st` by events, beside the others on `st`.
+  AuxLane* aux = d >= 2 && P.SL.laneb[0] ? aux_lane(st) : nullptr;
+  if (aux && (hipEventRecord(aux->fork, st) != hipSuccess ||
+              hipStreamWaitEvent(aux->st, aux->fork, 0) != hipSuccess))
+    return MACH_EDEVICE;
+  if (aux) {
+    const SolverLayout SB = solver_lane_b(P.SL);
+    if (launch_hosvd_mode(P.si, P.sp, SB, w, d - 1, ranks[d - 1], A_dev[d - 1], aux->st) != hipSuccess ||
+        hipEventRecord(aux->join, aux->st) != hipSuccess)
+      return MACH_EDEVICE;
+  }
+  for (int n = 0; n < (aux ? d - 1 : d); ++n)
     if (launch_hosvd_mode(P.si, P.sp, P.SL, w, n, ranks[n], A_dev[n], st) != hipSuccess)
       return MACH_EDEVICE;
+  if (aux && hipStreamWaitEvent(st, aux->join, 0) != hipSuccess) return MACH_EDEVICE;
   return MACH_OK;
 }
 

@@ -1348,7 +1348,7 @@ struct Ctx {
   const SampleHdr* hdr;
   hipStream_t st;
   int32_t* status() const { return (int32_t*)(ws + SL->status); }
-  int32_t* tags() const { return (int32_t*)(ws + SL->status + 16); }
+  int32_t* tags() const { return (int32_t*)(ws + SL->tags); }
   Status stat(bool with_done = false) const {
     Status s;
     s.hdr = hdr;
@@ -1544,7 +1544,10 @@ void sign_store(const Ctx& c, uint32_t I, uint32_t R, double* Aout, float* af) {
 
 hipError_t launch_solver_init(const SolverLayout& SL, char* ws, hipStream_t st) {
   hipLaunchKernelGGL(k_solver_init, dim3(1), dim3(64), 0, st, (int32_t*)(ws + SL.status),
-                     (int32_t*)(ws + SL.status + 16), 16);
+                     (int32_t*)(ws + SL.tags), 16);
+  if (SL.laneb[15])
+    hipLaunchKernelGGL(k_solver_init, dim3(1), dim3(64), 0, st, (int32_t*)(ws + SL.status),
+                       (int32_t*)(ws + SL.laneb[15]), 16);
   return hipGetLastError();
 }
 

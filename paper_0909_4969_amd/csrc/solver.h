@@ -64,6 +64,11 @@ struct SolverLayout {
   size_t part;                           // float64 64 x 64 x 64 partials
   size_t skpart;                         // float64 split-K partials of G * block
   size_t pv, pi;                         // column-max partials (1024 x 16)
+  size_t tags;                           // int32 tags of warm starts and early exits (16)
+  // A second copy of the scratch above (G .. tags), used by the HOSVD of the
+  // last mode when it runs on its own stream beside the other modes; 0 when
+  // there is none (d == 1).
+  size_t laneb[16];
   size_t total;
   ModePlan mp[kMaxD];
   uint32_t KT, KH, hosvd_s[kMaxD];
@@ -71,6 +76,8 @@ struct SolverLayout {
 };
 
 bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout* out);
+// The layout with the second scratch copy in place of the first.
+SolverLayout solver_lane_b(const SolverLayout& S);
 
 struct SparsePtrs {
   const SampleHdr* hdr;
