@@ -92,6 +92,7 @@ SampleLayout sample_layout(const ShapeInfo& si, uint64_t cap) {
   L.headrow = take((size_t)si.MH * 4);
   L.coo_t = take((size_t)cap * 8);
   L.scan_tmp = take(((size_t)si.MT * si.nrb / 4096 + si.nblk / 4096 + 2) * 4);
+  L.cscpos = take((size_t)cap * 4);
   L.total = o;
   return L;
 }
@@ -362,6 +363,7 @@ SparsePtrs sparse_ptrs(const char* ws, const SampleLayout& L) {
   p.rowptr = (const uint32_t*)(ws + L.rowptr);
   p.colptr = (const uint32_t*)(ws + L.colptr);
   p.csc_cnt = (const uint32_t*)(ws + L.csc_cnt);
+  p.cscpos = (const uint32_t*)(ws + L.cscpos);
   return p;
 }
 

@@ -179,44 +179,122 @@ hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream
 
 // Column-side Gram of the sampled unfolding when the mode is the single
 // tail mode: G[r][r'] = sum_c Xhat[r, c] Xhat[r', c] over the CSR rows r
-// (head rows) and tail columns c.  One wave per row r walks the row's
-// entries (c, v) in order; for each, its lanes take the entries (r', v')
-// of CSC column c and add v v' to a float64 accumulator of row r in LDS.
-// The entries of one column have distinct r', so lanes never collide, and
-// every accumulator is summed in column order.
+// (head rows) and tail columns c.  The CSC columns list their entries in
+// the head order of the CSC layout (position head_pos(r)), so the entries
+// of column c at or after row r in that order start at the entry (r, c)
+// itself, whose CSC position the layout build recorded (cscpos).  One wave per row r walks the row's
+// entries (c, v) in order; for each, its lanes take those entries (r', v')
+// of column c and add v v' to a float64 accumulator of row r in LDS.  The
+// entries of one column have distinct r', so lanes never collide, and every
+// accumulator is summed in column order.  Row r writes G[r][r'] for
+// head_pos(r') >= head_pos(r); k_gram_mirror fills the rest by symmetry.
+// Row r = v / 2 for even wave index v and MH - 1 - v / 2 for odd v, so every
+// workgroup holds long and short rows alike.
 constexpr uint32_t kSparseGramMaxRows = 2048;
 
-__global__ __launch_bounds__(256) void k_gram_rows_sparse(const Entry* __restrict__ coo_l,
+// Position of head row r (C order over the head modes) in the CSC head
+// order (si.headperm, outermost first).
+__device__ __forceinline__ uint32_t head_pos(const ShapeInfo& si, uint32_t r) {
+  uint32_t idx[kMaxD];
+  uint32_t rem = r;
+  for (int m = si.h - 1; m >= 0; --m) {
+    idx[m] = si.fdim[m].mod(rem);
+    rem = si.fdim[m].div(rem);
+  }
+  uint32_t t = 0;
+  for (int j = 0; j < si.h; ++j) {
+    const int m = si.headperm[j];
+    t = t * si.dims[m] + idx[m];
+  }
+  return t;
+}
+
+__global__ __launch_bounds__(256) void k_gram_rows_sparse(ShapeInfo si, const Entry* __restrict__ coo_l,
                                                           const uint32_t* __restrict__ rowptr,
                                                           const Entry* __restrict__ coo_t,
                                                           const uint32_t* __restrict__ colptr,
-                                                          uint32_t MH, uint32_t MT, FastDiv fMT,
+                                                          const uint32_t* __restrict__ cscpos,
                                                           double* __restrict__ G, const SampleHdr* hdr,
                                                           const int32_t* st_solver) {
   if (hdr->status != 0 || *st_solver != 0) return;
   __shared__ double acc[4][kSparseGramMaxRows];
+  const uint32_t MH = si.MH;
+  const FastDiv fMT = si.fMT;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const uint32_t r = blockIdx.x * 4 + w;
+  const uint32_t v = blockIdx.x * 4 + w;
+  const uint32_t r = (v & 1) ? MH - 1 - (v >> 1) : (v >> 1);
   double* row = acc[w];
   for (uint32_t j = lane; j < MH; j += 64) row[j] = 0.0;
   __builtin_amdgcn_wave_barrier();
-  if (r < MH) {
-    const uint32_t base = r * MT;
-    for (uint32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-      Entry a = coo_l[e];
-      const uint32_t c = a.l - base;
-      const double va = (double)a.v;
-      const uint32_t b1 = colptr[c + 1];
-      for (uint32_t f = colptr[c] + lane; f < b1; f += 64) {
-        Entry b = coo_t[f];
-        row[fMT.div(b.l)] += va * (double)b.v;
+  if (v < MH) {
+    const uint32_t base = r * fMT.d, pr = head_pos(si, r);
+    const uint32_t e1 = rowptr[r + 1];
+    for (uint32_t e0 = rowptr[r]; e0 < e1; e0 += 64) {
+      // lane i holds the descriptor of entry e0 + i: value, first and end
+      // position of its part of the column
+      const uint32_t e = e0 + lane;
+      uint32_t lo = 0, hi = 0;
+      float va = 0.0f;
+      if (e < e1) {
+        const Entry a = coo_l[e];
+        va = a.v;
+        lo = cscpos[e];
+        hi = colptr[a.l - base + 1];
       }
-      __builtin_amdgcn_wave_barrier();
+      const int cnt = (int)min(64u, e1 - e0);
+      for (int k = 0; k < cnt; k += 4) {
+        // first column chunk of four entries loaded before any is added
+        Entry b[4];
+        uint32_t f[4], h[4];
+        double vk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ku = min(k + u, cnt - 1);
+          f[u] = (uint32_t)__builtin_amdgcn_readlane((int)lo, ku) + lane;
+          h[u] = k + u < cnt ? (uint32_t)__builtin_amdgcn_readlane((int)hi, ku) : 0u;
+          vk[u] = (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, va), ku));
+          b[u] = f[u] < h[u] ? coo_t[f[u]] : Entry{0u, 0.0f};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (f[u] < h[u]) row[fMT.div(b[u].l)] += vk[u] * (double)b[u].v;
+          for (uint32_t g = f[u] + 64; g < h[u]; g += 64) {
+            const Entry bb = coo_t[g];
+            row[fMT.div(bb.l)] += vk[u] * (double)bb.v;
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
     }
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t j = lane; j < MH; j += 64)
+      if (head_pos(si, j) >= pr) G[(size_t)r * MH + j] = row[j];
   }
-  __builtin_amdgcn_wave_barrier();
-  if (r < MH)
-    for (uint32_t j = lane; j < MH; j += 64) G[(size_t)r * MH + j] = row[j];
+}
+
+// The entries G[x][y] with head_pos(y) < head_pos(x) from their transposes,
+// by pairs of 64 x 64 tiles (bi, bj) and (bj, bi), bi >= bj, through LDS.
+__global__ __launch_bounds__(256) void k_gram_mirror(ShapeInfo si, double* __restrict__ G,
+                                                     const SampleHdr* hdr, const int32_t* st_solver) {
+  if (hdr->status != 0 || *st_solver != 0) return;
+  __shared__ double ta[64][65], tb[64][65];
+  const uint32_t MH = si.MH, bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const uint32_t x = e >> 6, y = e & 63;
+    const uint32_t ar = bi * 64 + x, ac = bj * 64 + y, br = bj * 64 + x, bc = bi * 64 + y;
+    ta[x][y] = (ar < MH && ac < MH) ? G[(size_t)ar * MH + ac] : 0.0;
+    tb[x][y] = (br < MH && bc < MH) ? G[(size_t)br * MH + bc] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const uint32_t x = e >> 6, y = e & 63;
+    const uint32_t ar = bi * 64 + x, ac = bj * 64 + y;
+    if (ar < MH && ac < MH && head_pos(si, ac) < head_pos(si, ar)) G[(size_t)ar * MH + ac] = tb[y][x];
+    const uint32_t br = bj * 64 + x, bc = bi * 64 + y;
+    if (bi != bj && br < MH && bc < MH && head_pos(si, bc) < head_pos(si, br))
+      G[(size_t)br * MH + bc] = ta[y][x];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -401,8 +479,11 @@ bool sparse_tail_gram_ok(const ShapeInfo& si, const SolverLayout& SL, int n) {
 
 hipError_t launch_gram_tail_sparse(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
                                    char* ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_rows_sparse, dim3((si.MH + 3) / 4), dim3(256), 0, st, sp.coo_l, sp.rowptr,
-                     sp.coo_t, sp.colptr, si.MH, si.MT, si.fMT, (double*)(ws + SL.G), sp.hdr,
+  hipLaunchKernelGGL(k_gram_rows_sparse, dim3((si.MH + 3) / 4), dim3(256), 0, st, si, sp.coo_l,
+                     sp.rowptr, sp.coo_t, sp.colptr, sp.cscpos, (double*)(ws + SL.G), sp.hdr,
+                     (const int32_t*)(ws + SL.status));
+  const uint32_t nt = (si.MH + 63) / 64;
+  hipLaunchKernelGGL(k_gram_mirror, dim3(nt, nt), dim3(256), 0, st, si, (double*)(ws + SL.G), sp.hdr,
                      (const int32_t*)(ws + SL.status));
   return hipGetLastError();
 }

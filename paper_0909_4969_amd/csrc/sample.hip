@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void k_csc_fill(ShapeInfo si, const uint64_t* 
                                                   const uint32_t* __restrict__ cnt,
                                                   const Entry* __restrict__ coo_l,
                                                   Entry* __restrict__ coo_t, uint32_t* __restrict__ colptr,
-                                                  const SampleHdr* hdr) {
+                                                  uint32_t* __restrict__ cscpos, const SampleHdr* hdr) {
   uint32_t rb = blockIdx.y * 4 + (threadIdx.x >> 6);
   uint32_t c = blockIdx.x * 64 + (threadIdx.x & 63);
   if (rb >= si.nrb || c >= si.MT) return;
@@ -347,7 +347,10 @@ __global__ __launch_bounds__(256) void k_csc_fill(ShapeInfo si, const uint64_t* 
     if ((word >> b) & 1ull) {
       uint64_t below = b ? (word & ((~0ull) >> (64 - b))) : 0ull;
       uint64_t src = (uint64_t)wrank[l >> 6] + (uint32_t)__popcll(below);
-      if (src < cap && dest < cap) coo_t[dest] = coo_l[src];
+      if (src < cap && dest < cap) {
+        coo_t[dest] = coo_l[src];
+        cscpos[src] = (uint32_t)dest;
+      }
       ++dest;
     }
   }
@@ -393,7 +396,7 @@ hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, doubl
   hipLaunchKernelGGL(k_csc_count, g, dim3(256), 0, st, si, bitmap, headrow, csc_cnt);
   scan_u32(csc_cnt, si.MT * si.nrb, (uint32_t*)(ws + L.scan_tmp), st);
   hipLaunchKernelGGL(k_csc_fill, g, dim3(256), 0, st, si, bitmap, wrank, headrow, csc_cnt, coo_l,
-                     coo_t, colptr, hdr);
+                     coo_t, colptr, (uint32_t*)(ws + L.cscpos), hdr);
   return hipGetLastError();
 }
 

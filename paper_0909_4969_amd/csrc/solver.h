@@ -88,6 +88,7 @@ struct SparsePtrs {
   const uint32_t* rowptr;
   const uint32_t* colptr;
   const uint32_t* csc_cnt;
+  const uint32_t* cscpos;   // CSC position of each CSR (l-ordered) entry
 };
 
 SparsePtrs sparse_ptrs(const char* ws_sample, const SampleLayout& L);
