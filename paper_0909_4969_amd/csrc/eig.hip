@@ -90,7 +90,7 @@ struct JacArgs {
   const double* G;     // n x n symmetric: entry (x, y) = sum_c G[(x * n + y) * nchunk + c]
   uint32_t nchunk;
   uint32_t n;
-  double* V;           // in: warm start if *tag == tagval; out: eigenvectors (columns, sorted)
+  double* V;           // in: warm start if tagval != 0 and *tag == tagval; out: eigenvectors (columns, sorted)
   double* lam;         // out: eigenvalues, descending
   int32_t* tag;
   int32_t tagval;
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_small(JacArgs a) {
   if (a.s.skip()) return;
   __shared__ JacLds<NP> L;
   const int n = (int)a.n, tid = threadIdx.x;
-  const bool warm = (*a.tag == a.tagval);
+  const bool warm = a.tagval != 0 && *a.tag == a.tagval;
   for (int e = tid; e < NP * NP; e += NT) {
     int x = e / NP, y = e % NP;
     double g = 0.0;
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_small(JacArgs a) {
   jacobi_core<NP, NT>(L, n, a.rtop, &conv, a.tol2);
   jacobi_sort_store<NP, NT>(L, n, a.lam, a.V);
   if (tid == 0) {
-    *a.tag = a.tagval;
+    if (a.tagval != 0) *a.tag = a.tagval;
     if (!conv) atomicCAS(a.s.st, 0, MACH_ENOCONV);
   }
 }
@@ -1449,7 +1449,6 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
   if (b > s) b = s;
   int32_t* tags = c.tags();
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagDone, 0);
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagRR, 0);
   hipLaunchKernelGGL(k_ss_init, dim3(cdiv((uint64_t)s * b, 256)), dim3(256), 0, c.st, Q, kBlock, s,
                      b, tag, tagval, c.stat());
   // Buffers: the Ritz vectors of every Rayleigh-Ritz step go to Qr (so the
@@ -1487,7 +1486,10 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
     nchunk = cdiv(s, rows);
     hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, z, kBlock, w, kBlock, s, b, rows,
                        H, sd);
-    jacobi(c, H, nchunk, b, VH, lamH, tags + kTagRR, 0x52520000 | (int32_t)b, true, (int)R, 1e-28);
+    // The block is the previous Ritz vectors times G^8, orthonormalised in
+    // column order, so H is close to diagonal as it stands: start from the
+    // identity (the previous step's rotation would undo that).
+    jacobi(c, H, nchunk, b, VH, lamH, tags + kTagRR, 0, true, (int)R, 1e-24);
     double* zr = other(z, w);
     gemm(c, z, kBlock, VH, b, Qr, kBlock, s, b, b, true);
     gemm(c, w, kBlock, VH, b, zr, kBlock, s, b, b, true);
