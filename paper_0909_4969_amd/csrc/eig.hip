@@ -162,38 +162,45 @@ __device__ void block_sum2n(double& a, double& b, double (*red)[16]) {
   __syncthreads();
 }
 
-// D = op(A) B for NP x NP matrices in LDS (op(A) = A^T when TA), each of
-// the first (NP/4)^2 threads accumulating a 4 x 4 block in float64; D may
-// alias A or B (every read completes before the first write).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// D = op(A) B for NP x NP matrices in LDS (op(A) = A^T when TA) on float64
+// MFMA: each wave takes 16 x 16 output tiles and runs
+// v_mfma_f64_16x16x4f64 over the inner index in steps of 4 (operand lane
+// l: row / column l % 16, inner index l / 16; result register v of lane l:
+// row l / 16 + 4 v, column l % 16).  D may alias A or B (every read
+// completes before the first write).
 template <int NP, int NT, bool TA>
 __device__ void lds_gemm(double (*A)[NP + 1], double (*B)[NP + 1], double (*D)[NP + 1]) {
-  const int tid = threadIdx.x;
-  const bool own = tid < (NP / 4) * (NP / 4);
-  const int bx = (tid / (NP / 4)) * 4, by = (tid % (NP / 4)) * 4;
-  double acc[4][4];
+  constexpr int TT = NP / 16, NW = NT / 64, TPW = (TT * TT + NW - 1) / NW;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  v4d acc[TPW];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  if (own)
-    for (int z = 0; z < NP; ++z) {
-      double u[4], w[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        u[i] = TA ? A[z][bx + i] : A[bx + i][z];
-        w[i] = B[z][by + i];
+  for (int u = 0; u < TPW; ++u) {
+    const int t = w + u * NW;
+    acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (t < TT * TT) {
+      const int ti = t / TT, tj = t % TT;
+      v4d c = acc[u];
+#pragma unroll 4
+      for (int k0 = 0; k0 < NP; k0 += 4) {
+        const double av = TA ? A[k0 + lk][ti * 16 + li] : A[ti * 16 + li][k0 + lk];
+        const double bv = B[k0 + lk][tj * 16 + li];
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
+      acc[u] = c;
     }
+  }
   __syncthreads();
-  if (own)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+  for (int u = 0; u < TPW; ++u) {
+    const int t = w + u * NW;
+    if (t < TT * TT) {
+      const int ti = t / TT, tj = t % TT;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) D[bx + i][by + j] = acc[i][j];
+      for (int v = 0; v < 4; ++v) D[ti * 16 + lk + 4 * v][tj * 16 + li] = acc[u][v];
+    }
+  }
   __syncthreads();
 }
 
@@ -212,42 +219,9 @@ __device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin,
   warm = warm || in_lds;
   __syncthreads();
   if (!warm) return;
-  // W = G V, then A = V^T W; 4x4 register blocks per thread.
-  const int bx = (tid / (NP / 4)) * 4, by = (tid % (NP / 4)) * 4;
-  const bool own = tid < (NP / 4) * (NP / 4);
-  double acc[4][4];
-  if (own) {
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int z = 0; z < n; ++z) {
-      double u[4], w[4];
-      for (int i = 0; i < 4; ++i) {
-        u[i] = L.A[bx + i][z];
-        w[i] = L.V[z][by + i];
-      }
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
-    }
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) L.W[bx + i][by + j] = acc[i][j];
-  }
-  __syncthreads();
-  if (own) {
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int z = 0; z < n; ++z) {
-      double u[4], w[4];
-      for (int i = 0; i < 4; ++i) {
-        u[i] = L.V[z][bx + i];
-        w[i] = L.W[z][by + i];
-      }
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], w[j], acc[i][j]);
-    }
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) L.A[bx + i][by + j] = acc[i][j];
-  }
-  __syncthreads();
+  // W = G V, then A = V^T W (padding: G zero, V the identity)
+  lds_gemm<NP, NT, false>(L.A, L.V, L.W);
+  lds_gemm<NP, NT, true>(L.V, L.W, L.A);
   for (int e = tid; e < NP * NP; e += NT) {
     int x = e / NP, y = e % NP;
     if (x < y) {
