@@ -332,13 +332,14 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   S.pv = take(1024 * 16 * 8);
   S.pi = take(1024 * 16 * 4);
   S.tags = S.status + 16;
+  S.sred = take((size_t)kSredElems * 8);
   if (d >= 2) {   // second scratch copy for the last mode's HOSVD
-    const size_t sz[16] = {gmax * 8, S.Gpart_elems * 8, (size_t)imax * 16 * 8,
+    const size_t sz[17] = {gmax * 8, S.Gpart_elems * 8, (size_t)imax * 16 * 8,
                            (size_t)zrows * kBlock * 8, (size_t)zrows * kBlock * 8,
                            (size_t)zrows * kBlock * 8, (size_t)zrows * kBlock * 8, 64 * 64 * 8,
                            64 * 64 * 8, 64 * 64 * 8, 64 * 8, 64 * 64 * 64 * 8, skmax * 8,
-                           1024 * 16 * 8, 1024 * 16 * 4, 256};
-    for (int f = 0; f < 16; ++f) S.laneb[f] = take(sz[f]);
+                           1024 * 16 * 8, 1024 * 16 * 4, 256, (size_t)kSredElems * 8};
+    for (int f = 0; f < 17; ++f) S.laneb[f] = take(sz[f]);
   }
   S.total = o;
   *out = S;
@@ -347,9 +348,9 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
 
 SolverLayout solver_lane_b(const SolverLayout& S) {
   SolverLayout B = S;
-  size_t* f[16] = {&B.G, &B.Gpart, &B.Aw, &B.Zs, &B.Z2s, &B.Qrs, &B.Qhs, &B.H,
-                   &B.VH, &B.small, &B.lamH, &B.part, &B.skpart, &B.pv, &B.pi, &B.tags};
-  for (int i = 0; i < 16; ++i) *f[i] = S.laneb[i];
+  size_t* f[17] = {&B.G, &B.Gpart, &B.Aw, &B.Zs, &B.Z2s, &B.Qrs, &B.Qhs, &B.H,   &B.VH,
+                   &B.small, &B.lamH, &B.part, &B.skpart, &B.pv, &B.pi, &B.tags, &B.sred};
+  for (int i = 0; i < 17; ++i) *f[i] = S.laneb[i];
   return B;
 }
 

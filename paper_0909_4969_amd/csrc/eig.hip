@@ -444,6 +444,32 @@ __global__ __launch_bounds__(256) void k_ctc_partial(CtcArgs a, double* __restri
   part[((size_t)slot * 256 + threadIdx.x) * kCtcChunks + blockIdx.x] = acc;   // chunks < nch[slot] used
 }
 
+// Sums of chunked partials, one wave per entry: lane c adds chunks c,
+// c + 64, ... of entry e (in[e * es + c * cs]), then a fixed butterfly adds
+// the lanes; out[e] gets the total.  Entries come in groups of gsize with
+// their own chunk counts nch[e / gsize] (at most 4 groups).  The order of
+// the additions is fixed, so the result is reproducible.
+struct ReduceArgs {
+  const double* in;
+  double* out;
+  uint32_t nent, gsize, es, cs;
+  uint32_t nch[4];
+};
+
+__global__ __launch_bounds__(256) void k_reduce_chunks(ReduceArgs a, Status s) {
+  if (s.skip()) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= a.nent) return;
+  const uint32_t nc = a.nch[e / a.gsize];
+  const double* p = a.in + (size_t)e * a.es;
+  double v = 0.0;
+  for (uint32_t c = lane; c < nc; c += 64) v += p[(size_t)c * a.cs];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) a.out[e] = v;
+}
+
 // One mode update of a HOOI sweep, sides up to 64, in one workgroup:
 // G = sum of the Gram partials (fixed order); warm-started Jacobi; the
 // eigenpairs sorted and kept for the next sweep.  Row-side Gram: the top R
@@ -455,6 +481,7 @@ struct SolveArgs {
   uint32_t nchunk, s, I, R;
   int kside;
   const double* ctc;      // column side: C_j partials of the other modes (k_ctc_partial), or null
+  uint32_t cstride;       // entry stride of ctc (chunks per entry)
   int nother;              // other modes: ranks, column strides in Y_(k), C_j chunks
   uint32_t oR[3], ost[3], onch[3];
   double* V;
@@ -490,7 +517,7 @@ __global__ __launch_bounds__(NT) void k_mode_solve(SolveArgs a) {
   if (warm && a.ctc) {
     __shared__ double Cj[3][16][17];
     for (int e = tid; e < a.nother * 256; e += NT) {
-      const double* p = a.ctc + (size_t)e * kCtcChunks;
+      const double* p = a.ctc + (size_t)e * a.cstride;
       const uint32_t nc = a.onch[e >> 8];
       double v = 0.0;
 #pragma unroll 8
@@ -628,9 +655,14 @@ __global__ __launch_bounds__(256) void k_bp_tall(const float* __restrict__ Y, ui
   for (int r = 0; r < 16; ++r) rows[threadIdx.x][r] = (i < I && (uint32_t)r < R) ? acc[r] : 0.0;
   __syncthreads();
   const int x = threadIdx.x >> 4, y = threadIdx.x & 15;
-  double g = 0.0;
-  for (int t = 0; t < 256; ++t) g = fma(rows[t][x], rows[t][y], g);
-  part[(size_t)blockIdx.x * 256 + threadIdx.x] = g;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+  for (int t = 0; t < 256; t += 4) {
+    g0 = fma(rows[t][x], rows[t][y], g0);
+    g1 = fma(rows[t + 1][x], rows[t + 1][y], g1);
+    g2 = fma(rows[t + 2][x], rows[t + 2][y], g2);
+    g3 = fma(rows[t + 3][x], rows[t + 3][y], g3);
+  }
+  part[(size_t)blockIdx.x * 256 + threadIdx.x] = (g0 + g1) + (g2 + g3);
 }
 
 // One Cholesky-QR pass on Aw (I x 16): every workgroup sums the Gram
@@ -1486,9 +1518,31 @@ __global__ __launch_bounds__(256) void k_ata16_partial(const double* __restrict_
   for (int r = 0; r < 16; ++r) rows[threadIdx.x][r] = i < I ? Aw[(size_t)i * 16 + r] : 0.0;
   __syncthreads();
   const int x = threadIdx.x >> 4, y = threadIdx.x & 15;
-  double g = 0.0;
-  for (int t = 0; t < 256; ++t) g = fma(rows[t][x], rows[t][y], g);
-  part[(size_t)blockIdx.x * 256 + threadIdx.x] = g;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+  for (int t = 0; t < 256; t += 4) {
+    g0 = fma(rows[t][x], rows[t][y], g0);
+    g1 = fma(rows[t + 1][x], rows[t + 1][y], g1);
+    g2 = fma(rows[t + 2][x], rows[t + 2][y], g2);
+    g3 = fma(rows[t + 3][x], rows[t + 3][y], g3);
+  }
+  part[(size_t)blockIdx.x * 256 + threadIdx.x] = (g0 + g1) + (g2 + g3);
+}
+
+// The 16 x 16 Gram of a tall factor from its per-workgroup partials
+// (chunk-major, 256 entries each): summed into sred once when there are
+// several, so that every workgroup of the apply step reads one copy.
+const double* reduce_tall(const Ctx& c, const double* part, uint32_t nwg) {
+  if (nwg <= 1) return part;
+  ReduceArgs r{};
+  r.in = part;
+  r.out = c.d(c.SL->sred) + kSredTall;
+  r.nent = 256;
+  r.gsize = 256;
+  r.es = 1;
+  r.cs = 256;
+  r.nch[0] = nwg;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3(64), dim3(256), 0, c.st, r, c.stat());
+  return r.out;
 }
 
 // Aw (I x 16, nearly orthonormal columns) -> one Cholesky-QR pass, the sign
@@ -1497,7 +1551,8 @@ void finish_factor(const Ctx& c, uint32_t I, uint32_t R, double* Aout, float* af
   uint32_t nwg = cdiv(I, 256);
   double* part = c.d(c.SL->part);
   hipLaunchKernelGGL(k_ata16_partial, dim3(nwg), dim3(256), 0, c.st, c.d(c.SL->Aw), I, part, c.stat());
-  hipLaunchKernelGGL(k_chol_apply_tall, dim3(nwg), dim3(256), 0, c.st, c.d(c.SL->Aw), I, R, part, nwg,
+  const double* g16 = reduce_tall(c, part, nwg);
+  hipLaunchKernelGGL(k_chol_apply_tall, dim3(nwg), dim3(256), 0, c.st, c.d(c.SL->Aw), I, R, g16, 1u,
                      c.d(c.SL->pv), (uint32_t*)(c.ws + c.SL->pi), c.stat());
   hipLaunchKernelGGL(k_sign_store, dim3(cdiv((uint64_t)I * 16, 256)), dim3(256), 0, c.st, c.d(c.SL->Aw),
                      I, R, c.d(c.SL->pv), (const uint32_t*)(c.ws + c.SL->pi), nwg, Aout, af, c.stat());
@@ -1539,6 +1594,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     SolveArgs a;
     a.part = c.d(SL.Gpart);
     a.ctc = nullptr;
+    a.cstride = kCtcChunks;
     a.nother = 0;
     if (m.kside) {
       CtcArgs ca{};
@@ -1554,9 +1610,36 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
         ++ca.n;
       }
       a.nother = ca.n;
-      a.ctc = c.d(SL.part);
       hipLaunchKernelGGL(k_ctc_partial, dim3(kCtcChunks, ca.n), dim3(256), 0, st, ca, c.d(SL.part),
                          c.stat());
+      // C_j of every other mode summed once (one wave per entry)
+      ReduceArgs r{};
+      r.in = c.d(SL.part);
+      r.out = c.d(SL.sred) + kSredCtc;
+      r.nent = 256 * ca.n;
+      r.gsize = 256;
+      r.es = kCtcChunks;
+      r.cs = 1;
+      for (int j = 0; j < ca.n; ++j) {
+        r.nch[j] = ca.nch[j];
+        a.onch[j] = 1;
+      }
+      hipLaunchKernelGGL(k_reduce_chunks, dim3(cdiv(r.nent, 4)), dim3(256), 0, st, r, c.stat());
+      a.ctc = r.out;
+      a.cstride = 1;
+    }
+    if (nchunk > 1) {   // the Gram partials likewise
+      ReduceArgs r{};
+      r.in = c.d(SL.Gpart);
+      r.out = c.d(SL.sred) + kSredGram;
+      r.nent = m.s * m.s;
+      r.gsize = r.nent;
+      r.es = nchunk;
+      r.cs = 1;
+      r.nch[0] = nchunk;
+      hipLaunchKernelGGL(k_reduce_chunks, dim3(cdiv(r.nent, 4)), dim3(256), 0, st, r, c.stat());
+      a.part = r.out;
+      nchunk = 1;
     }
     a.nchunk = nchunk;
     a.s = m.s;
@@ -1595,7 +1678,8 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
       double* part = c.d(SL.part);
       hipLaunchKernelGGL(k_bp_tall, dim3(nwg), dim3(256), 0, st, (const float*)(ws + m.ybuf), m.O, m.I,
                          m.Q, c.d(SL.small), m.R, c.d(SL.Aw), part, c.stat());
-      hipLaunchKernelGGL(k_chol_apply_tall, dim3(nwg), dim3(256), 0, st, c.d(SL.Aw), m.I, m.R, part, nwg,
+      const double* g16 = reduce_tall(c, part, nwg);
+      hipLaunchKernelGGL(k_chol_apply_tall, dim3(nwg), dim3(256), 0, st, c.d(SL.Aw), m.I, m.R, g16, 1u,
                          c.d(SL.pv), (uint32_t*)(ws + SL.pi), c.stat());
       hipLaunchKernelGGL(k_sign_store, dim3(cdiv((uint64_t)m.I * 16, 256)), dim3(256), 0, st,
                          c.d(SL.Aw), m.I, m.R, c.d(SL.pv), (const uint32_t*)(ws + SL.pi), nwg, A_out,

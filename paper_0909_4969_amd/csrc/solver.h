@@ -41,6 +41,9 @@ struct ModePlan {
 };
 
 constexpr uint32_t kBlock = 64;          // subspace block for sides > kSmallEig
+// sred: Gram of a sweep mode (64 x 64), C_j of up to 3 other modes (3 x 256),
+// 16 x 16 Gram of a tall factor
+constexpr uint32_t kSredGram = 0, kSredCtc = 4096, kSredTall = 4096 + 768, kSredElems = 4096 + 768 + 256;
 constexpr uint32_t kSplitK = 256;        // summation slice of the split products by G
 constexpr uint32_t kMfmaGramMaxRows = 1024;  // row-side HOSVD Grams on MFMA up to this side
 
@@ -65,10 +68,11 @@ struct SolverLayout {
   size_t skpart;                         // float64 split-K partials of G * block
   size_t pv, pi;                         // column-max partials (1024 x 16)
   size_t tags;                           // int32 tags of warm starts and early exits (16)
-  // A second copy of the scratch above (G .. tags), used by the HOSVD of the
+  size_t sred;                           // float64 reduced partials (kSredElems)
+  // A second copy of the scratch above (G .. sred), used by the HOSVD of the
   // last mode when it runs on its own stream beside the other modes; 0 when
   // there is none (d == 1).
-  size_t laneb[16];
+  size_t laneb[17];
   size_t total;
   ModePlan mp[kMaxD];
   uint32_t KT, KH, hosvd_s[kMaxD];
