@@ -71,28 +71,43 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a, Load ld) {
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (uint32_t zs = zc0; zs < zc1; zs += 32) {
-    // stage 32 summation indices x 64 Gram indices for both tiles
-    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-      int zz = e >> 6, xx = e & 63;
-      uint32_t z = zs + zz;
+  // diagonal tiles (x0 == y0) stage one matrix; the next 32 summation
+  // indices are loaded into registers while the current ones are used
+  const bool same = x0 == y0;
+  auto fetch = [&](uint32_t zs, float* px, float* py) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + 256 * u, zz = e >> 6, xx = e & 63;
+      const uint32_t z = zs + zz;
       float vx = 0.f, vy = 0.f;
       if (z < zc1) {
-        uint32_t x = x0 + xx, y = y0 + xx;
+        const uint32_t x = x0 + xx, y = y0 + xx;
         if (a.kside) {
-          uint32_t zo = z * a.Q;
+          const uint32_t zo = z * a.Q;
           if (x < a.X) vx = ld(zo + col_off(a, x));
-          if (y < a.X) vy = ld(zo + col_off(a, y));
+          if (!same && y < a.X) vy = ld(zo + col_off(a, y));
         } else {
-          uint32_t zo = col_off(a, z);
+          const uint32_t zo = col_off(a, z);
           if (x < a.X) vx = ld(zo + x * a.Q);
-          if (y < a.X) vy = ld(zo + y * a.Q);
+          if (!same && y < a.X) vy = ld(zo + y * a.Q);
         }
       }
-      Mx[zz][xx] = vx;
-      My[zz][xx] = vy;
+      px[u] = vx;
+      py[u] = vy;
+    }
+  };
+  float px[8], py[8];
+  fetch(zc0, px, py);
+  for (uint32_t zs = zc0; zs < zc1; zs += 32) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      Mx[e >> 6][e & 63] = px[u];
+      if (!same) My[e >> 6][e & 63] = py[u];
     }
     __syncthreads();
+    if (zs + 32 < zc1) fetch(zs + 32, px, py);
+    float (*Ny)[65] = same ? Mx : My;
     float c[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -104,7 +119,7 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a, Load ld) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         u[i] = Mx[zz][tx * 4 + i];
-        w[i] = My[zz][ty * 4 + i];
+        w[i] = Ny[zz][ty * 4 + i];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
