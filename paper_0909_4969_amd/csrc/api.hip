@@ -93,6 +93,7 @@ SampleLayout sample_layout(const ShapeInfo& si, uint64_t cap) {
   L.coo_t = take((size_t)cap * 8);
   L.scan_tmp = take(((size_t)si.MT * si.nrb / 4096 + si.nblk / 4096 + 2) * 4);
   L.cscpos = take((size_t)cap * 4);
+  L.headpos = take((size_t)si.MH * 4);
   L.total = o;
   return L;
 }
@@ -365,6 +366,7 @@ SparsePtrs sparse_ptrs(const char* ws, const SampleLayout& L) {
   p.colptr = (const uint32_t*)(ws + L.colptr);
   p.csc_cnt = (const uint32_t*)(ws + L.csc_cnt);
   p.cscpos = (const uint32_t*)(ws + L.cscpos);
+  p.headpos = (const uint32_t*)(ws + L.headpos);
   return p;
 }
 

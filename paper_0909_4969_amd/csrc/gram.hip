@@ -195,36 +195,21 @@ hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream
 // Column-side Gram of the sampled unfolding when the mode is the single
 // tail mode: G[r][r'] = sum_c Xhat[r, c] Xhat[r', c] over the CSR rows r
 // (head rows) and tail columns c.  The CSC columns list their entries in
-// the head order of the CSC layout (position head_pos(r)), so the entries
+// the head order of the CSC layout (position headpos[r]), so the entries
 // of column c at or after row r in that order start at the entry (r, c)
 // itself, whose CSC position the layout build recorded (cscpos).  One wave per row r walks the row's
 // entries (c, v) in order; for each, its lanes take those entries (r', v')
 // of column c and add v v' to a float64 accumulator of row r in LDS.  The
 // entries of one column have distinct r', so lanes never collide, and every
 // accumulator is summed in column order.  Row r writes G[r][r'] for
-// head_pos(r') >= head_pos(r); k_gram_mirror fills the rest by symmetry.
+// headpos[r'] >= headpos[r]; k_gram_mirror fills the rest by symmetry.
 // Row r = v / 2 for even wave index v and MH - 1 - v / 2 for odd v, so every
 // workgroup holds long and short rows alike.
 constexpr uint32_t kSparseGramMaxRows = 2048;
 
-// Position of head row r (C order over the head modes) in the CSC head
-// order (si.headperm, outermost first).
-__device__ __forceinline__ uint32_t head_pos(const ShapeInfo& si, uint32_t r) {
-  uint32_t idx[kMaxD];
-  uint32_t rem = r;
-  for (int m = si.h - 1; m >= 0; --m) {
-    idx[m] = si.fdim[m].mod(rem);
-    rem = si.fdim[m].div(rem);
-  }
-  uint32_t t = 0;
-  for (int j = 0; j < si.h; ++j) {
-    const int m = si.headperm[j];
-    t = t * si.dims[m] + idx[m];
-  }
-  return t;
-}
-
-__global__ __launch_bounds__(256) void k_gram_rows_sparse(ShapeInfo si, const Entry* __restrict__ coo_l,
+__global__ __launch_bounds__(256) void k_gram_rows_sparse(uint32_t MH, FastDiv fMT,
+                                                          const uint32_t* __restrict__ headpos,
+                                                          const Entry* __restrict__ coo_l,
                                                           const uint32_t* __restrict__ rowptr,
                                                           const Entry* __restrict__ coo_t,
                                                           const uint32_t* __restrict__ colptr,
@@ -233,8 +218,6 @@ __global__ __launch_bounds__(256) void k_gram_rows_sparse(ShapeInfo si, const En
                                                           const int32_t* st_solver) {
   if (hdr->status != 0 || *st_solver != 0) return;
   __shared__ double acc[4][kSparseGramMaxRows];
-  const uint32_t MH = si.MH;
-  const FastDiv fMT = si.fMT;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t v = blockIdx.x * 4 + w;
   const uint32_t r = (v & 1) ? MH - 1 - (v >> 1) : (v >> 1);
@@ -242,7 +225,7 @@ __global__ __launch_bounds__(256) void k_gram_rows_sparse(ShapeInfo si, const En
   for (uint32_t j = lane; j < MH; j += 64) row[j] = 0.0;
   __builtin_amdgcn_wave_barrier();
   if (v < MH) {
-    const uint32_t base = r * fMT.d, pr = head_pos(si, r);
+    const uint32_t base = r * fMT.d, pr = headpos[r];
     const uint32_t e1 = rowptr[r + 1];
     for (uint32_t e0 = rowptr[r]; e0 < e1; e0 += 64) {
       // lane i holds the descriptor of entry e0 + i: value, first and end
@@ -283,18 +266,25 @@ __global__ __launch_bounds__(256) void k_gram_rows_sparse(ShapeInfo si, const En
     }
     __builtin_amdgcn_wave_barrier();
     for (uint32_t j = lane; j < MH; j += 64)
-      if (head_pos(si, j) >= pr) G[(size_t)r * MH + j] = row[j];
+      if (headpos[j] >= pr) G[(size_t)r * MH + j] = row[j];
   }
 }
 
-// The entries G[x][y] with head_pos(y) < head_pos(x) from their transposes,
+// The entries G[x][y] with headpos[y] < headpos[x] from their transposes,
 // by pairs of 64 x 64 tiles (bi, bj) and (bj, bi), bi >= bj, through LDS.
-__global__ __launch_bounds__(256) void k_gram_mirror(ShapeInfo si, double* __restrict__ G,
-                                                     const SampleHdr* hdr, const int32_t* st_solver) {
+__global__ __launch_bounds__(256) void k_gram_mirror(uint32_t MH, const uint32_t* __restrict__ headpos,
+                                                     double* __restrict__ G, const SampleHdr* hdr,
+                                                     const int32_t* st_solver) {
   if (hdr->status != 0 || *st_solver != 0) return;
   __shared__ double ta[64][65], tb[64][65];
-  const uint32_t MH = si.MH, bi = blockIdx.y, bj = blockIdx.x;
+  __shared__ uint32_t pi_[64], pj[64];
+  const uint32_t bi = blockIdx.y, bj = blockIdx.x;
   if (bj > bi) return;
+  if (threadIdx.x < 64) {
+    const uint32_t i = bi * 64 + threadIdx.x, j = bj * 64 + threadIdx.x;
+    pi_[threadIdx.x] = i < MH ? headpos[i] : 0u;
+    pj[threadIdx.x] = j < MH ? headpos[j] : 0u;
+  }
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const uint32_t x = e >> 6, y = e & 63;
     const uint32_t ar = bi * 64 + x, ac = bj * 64 + y, br = bj * 64 + x, bc = bi * 64 + y;
@@ -305,10 +295,9 @@ __global__ __launch_bounds__(256) void k_gram_mirror(ShapeInfo si, double* __res
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const uint32_t x = e >> 6, y = e & 63;
     const uint32_t ar = bi * 64 + x, ac = bj * 64 + y;
-    if (ar < MH && ac < MH && head_pos(si, ac) < head_pos(si, ar)) G[(size_t)ar * MH + ac] = tb[y][x];
+    if (ar < MH && ac < MH && pj[y] < pi_[x]) G[(size_t)ar * MH + ac] = tb[y][x];
     const uint32_t br = bj * 64 + x, bc = bi * 64 + y;
-    if (bi != bj && br < MH && bc < MH && head_pos(si, bc) < head_pos(si, br))
-      G[(size_t)br * MH + bc] = ta[y][x];
+    if (bi != bj && br < MH && bc < MH && pi_[y] < pj[x]) G[(size_t)br * MH + bc] = ta[y][x];
   }
 }
 
@@ -494,12 +483,12 @@ bool sparse_tail_gram_ok(const ShapeInfo& si, const SolverLayout& SL, int n) {
 
 hipError_t launch_gram_tail_sparse(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
                                    char* ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_rows_sparse, dim3((si.MH + 3) / 4), dim3(256), 0, st, si, sp.coo_l,
-                     sp.rowptr, sp.coo_t, sp.colptr, sp.cscpos, (double*)(ws + SL.G), sp.hdr,
-                     (const int32_t*)(ws + SL.status));
+  hipLaunchKernelGGL(k_gram_rows_sparse, dim3((si.MH + 3) / 4), dim3(256), 0, st, si.MH, si.fMT,
+                     sp.headpos, sp.coo_l, sp.rowptr, sp.coo_t, sp.colptr, sp.cscpos,
+                     (double*)(ws + SL.G), sp.hdr, (const int32_t*)(ws + SL.status));
   const uint32_t nt = (si.MH + 63) / 64;
-  hipLaunchKernelGGL(k_gram_mirror, dim3(nt, nt), dim3(256), 0, st, si, (double*)(ws + SL.G), sp.hdr,
-                     (const int32_t*)(ws + SL.status));
+  hipLaunchKernelGGL(k_gram_mirror, dim3(nt, nt), dim3(256), 0, st, si.MH, sp.headpos,
+                     (double*)(ws + SL.G), sp.hdr, (const int32_t*)(ws + SL.status));
   return hipGetLastError();
 }
 

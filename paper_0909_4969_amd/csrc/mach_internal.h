@@ -84,7 +84,7 @@ constexpr int32_t kSampleMagic = 0x4d414348;   // "MACH"
 
 struct SampleLayout {
   size_t hdr, bitmap, wrank, blkcnt, sumsq_part, coo_l, rowptr, colptr,
-      csc_cnt, headrow, coo_t, scan_tmp, cscpos, total;
+      csc_cnt, headrow, coo_t, scan_tmp, cscpos, headpos, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

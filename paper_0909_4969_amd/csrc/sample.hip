@@ -293,7 +293,7 @@ __global__ void k_rowptr(ShapeInfo si, const uint64_t* __restrict__ bitmap,
 }
 
 // headrow[t] = C-order head row index of position t in headperm order.
-__global__ void k_headrow(ShapeInfo si, uint32_t* __restrict__ headrow) {
+__global__ void k_headrow(ShapeInfo si, uint32_t* __restrict__ headrow, uint32_t* __restrict__ headpos) {
   uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= si.MH) return;
   uint32_t rem = t, r = 0;
@@ -304,6 +304,7 @@ __global__ void k_headrow(ShapeInfo si, uint32_t* __restrict__ headrow) {
     r += i * (si.stride[m] / si.MT);
   }
   headrow[t] = r;
+  headpos[r] = t;
 }
 
 // Wave = (64 consecutive tail columns) x (one block of rb head rows).
@@ -391,7 +392,8 @@ hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, doubl
                      sumsq_part, wrank, si.nwords);
   hipLaunchKernelGGL(k_rowptr, dim3((si.MH + 1 + 255) / 256), dim3(256), 0, st, si, bitmap,
                      wrank, hdr, rowptr);
-  hipLaunchKernelGGL(k_headrow, dim3((si.MH + 255) / 256), dim3(256), 0, st, si, headrow);
+  hipLaunchKernelGGL(k_headrow, dim3((si.MH + 255) / 256), dim3(256), 0, st, si, headrow,
+                     (uint32_t*)(ws + L.headpos));
   dim3 g((si.MT + 63) / 64, (si.nrb + 3) / 4);
   hipLaunchKernelGGL(k_csc_count, g, dim3(256), 0, st, si, bitmap, headrow, csc_cnt);
   scan_u32(csc_cnt, si.MT * si.nrb, (uint32_t*)(ws + L.scan_tmp), st);

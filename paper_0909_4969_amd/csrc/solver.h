@@ -93,6 +93,7 @@ struct SparsePtrs {
   const uint32_t* colptr;
   const uint32_t* csc_cnt;
   const uint32_t* cscpos;   // CSC position of each CSR (l-ordered) entry
+  const uint32_t* headpos;  // position of each head row in the CSC head order
 };
 
 SparsePtrs sparse_ptrs(const char* ws_sample, const SampleLayout& L);
