@@ -27,8 +27,9 @@
  *    rescale of the kept entries.
  *  - Device pointers are plain device addresses (e.g. a torch tensor's
  *    data_ptr()); `stream` is a hipStream_t passed as void* (NULL = the
- *    null stream).  Every call only enqueues work on `stream` and returns;
- *    nothing synchronises except mach_read_status.
+ *    null stream).  Every call only enqueues work on `stream` (mach_hosvd
+ *    also on an internal stream joined back into it) and returns; nothing
+ *    synchronises except mach_read_status.
  *  - The library allocates nothing.  The caller owns every buffer, sized
  *    with the *_workspace_bytes queries; a workspace may be reused for any
  *    later call with the same shape, ranks and capacity.  Two calls that
@@ -113,7 +114,12 @@ size_t mach_solver_workspace_bytes(const mach_shape* s, const int32_t* ranks,
  * float64 row-major, written.  nnz_cap is the capacity ws_sample was built
  * with (it fixes where the sparse arrays sit).  Requires
  * 1 <= R_n <= min(I_n, N / I_n, 16) and d <= 4.  Resets the solver
- * workspace first. */
+ * workspace first.  The last mode's HOSVD runs on an auxiliary HIP stream
+ * (one per caller stream and device, created on the first call, default
+ * priority, kept for the life of the process), forked from and joined into
+ * `stream` by events: work enqueued on `stream` after the call still sees
+ * every factor; the call remains asynchronous.  If the auxiliary stream
+ * cannot be created, all modes run on `stream`. */
 mach_status mach_hosvd(const void* ws_sample, uint64_t nnz_cap, const mach_shape* s,
                        const int32_t* ranks, double* const* A_dev, void* ws, size_t ws_bytes,
                        void* stream);
