@@ -843,6 +843,40 @@ __global__ __launch_bounds__(256) void k_atb_partial(const double* __restrict__ 
     }
 }
 
+// Degree-2 Chebyshev filter of the subspace iteration, applied as the
+// epilogue of the products by G: with tau the smallest Ritz value of the last
+// Rayleigh-Ritz step, t(x) = 2 x / tau - 1 maps [0, tau] onto [-1, 1], and
+// two steps give T_2(t(G)) X = 2 t(G) Y1 - X with Y1 = t(G) X, which damps
+// every eigenvalue below tau to at most 1 while the wanted ones grow like
+// 8 (lambda / tau)^2 (plain power steps grow them like (lambda / tau)^2).
+// out = alpha G X + beta X + gamma Xp: step 1 (2 / tau, -1, 0), step 2
+// (4 / tau, -2, -1) with X = Y1 and Xp the first step's input; plain
+// (1, 0, 0) until a Ritz value is known (*valid == 0) or if tau <= 0.
+struct Cheb {
+  int step;               // 0: plain product, 1 or 2: filter step
+  const double* lam;      // Ritz values of the last Rayleigh-Ritz step
+  uint32_t bidx;          // index of the smallest one (block size - 1)
+  const int32_t* valid;   // nonzero once lam holds Ritz values
+  const double* Xp;       // input of step 1 (step 2 only), ld kBlock
+};
+
+__device__ __forceinline__ void cheb_coef(const Cheb& ch, double* al, double* be, double* ga) {
+  *al = 1.0;
+  *be = 0.0;
+  *ga = 0.0;
+  if (ch.step == 0 || !ch.valid || *ch.valid == 0) return;
+  const double tau = ch.lam[ch.bidx];
+  if (!(tau > 0.0) || !isfinite(tau)) return;
+  if (ch.step == 1) {
+    *al = 2.0 / tau;
+    *be = -1.0;
+  } else {
+    *al = 4.0 / tau;
+    *be = -2.0;
+    *ga = -1.0;
+  }
+}
+
 // C[M x N] partials of A[M x K] * B[K x N] (row-major, N <= 64) for long K:
 // workgroup (x, y) owns rows 64x..64x+63 and the summation slice
 // [y * kSplitK, (y + 1) * kSplitK) (a single slice covers all of K);
@@ -851,7 +885,7 @@ __global__ __launch_bounds__(256) void k_atb_partial(const double* __restrict__ 
 __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ A, uint32_t lda,
                                                      const double* __restrict__ B, uint32_t ldb,
                                                      double* __restrict__ P, uint32_t M, uint32_t K,
-                                                     uint32_t N, Status s) {
+                                                     uint32_t N, Cheb ch, Status s) {
   if (s.skip()) return;
   __shared__ double As[32][68];
   __shared__ double Bs[32][68];
@@ -897,24 +931,40 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ 
     __syncthreads();
   }
   double* o = P + ((size_t)blockIdx.y * M + m0) * 64;
+  double al = 1.0, be = 0.0, ga = 0.0;
+  if (gridDim.y == 1) cheb_coef(ch, &al, &be, &ga);   // single slice: P is the output
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t r = ty * 4 + i;
     if (m0 + r < M)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) o[(size_t)r * 64 + tx * 4 + j] = acc[i][j];
+      for (int j = 0; j < 4; ++j) {
+        const size_t e = (size_t)(m0 + r) * ldb + tx * 4 + j;
+        double v = al * acc[i][j];
+        if (be != 0.0) v = fma(be, B[e], v);
+        if (ga != 0.0) v = fma(ga, ch.Xp[e], v);
+        o[(size_t)r * 64 + tx * 4 + j] = v;
+      }
   }
 }
 
-// C[m][n] = sum over the nks slices of P[slice][m][n] (fixed order), n < 64.
+// C[m][n] = sum over the nks slices of P[slice][m][n] (fixed order), n < 64,
+// then the filter epilogue (X: the product's right operand, ld ldc).
 __global__ void k_splitk_reduce(const double* __restrict__ P, uint32_t nks, uint32_t M,
-                                double* __restrict__ C, uint32_t ldc, Status s) {
+                                double* __restrict__ C, uint32_t ldc, const double* __restrict__ X,
+                                Cheb ch, Status s) {
   if (s.skip()) return;
   const uint32_t e = blockIdx.x * 256 + threadIdx.x;
   if (e >= M * 64) return;
   double acc = 0.0;
   for (uint32_t k = 0; k < nks; ++k) acc += P[(size_t)k * M * 64 + e];
-  C[(size_t)(e >> 6) * ldc + (e & 63)] = acc;
+  double al, be, ga;
+  cheb_coef(ch, &al, &be, &ga);
+  const size_t o = (size_t)(e >> 6) * ldc + (e & 63);
+  double v = al * acc;
+  if (be != 0.0) v = fma(be, X[o], v);
+  if (ga != 0.0) v = fma(ga, ch.Xp[o], v);
+  C[o] = v;
 }
 
 // Cholesky-QR helper for an n x n Gram (n <= 64) summed from its chunk-minor
@@ -1062,7 +1112,8 @@ __global__ void k_copy64(const double* __restrict__ src, double* __restrict__ ds
 __global__ __launch_bounds__(256) void k_ss_check(const double* __restrict__ Z2, const double* __restrict__ Qr,
                                                   uint32_t ld, uint32_t M, const double* __restrict__ theta,
                                                   uint32_t R, double tol, int32_t* done, int last,
-                                                  int32_t* stat_it, int32_t it, Status s) {
+                                                  int32_t* stat_it, int32_t it, int32_t* ritz,
+                                                  Status s) {
   if (s.skip()) return;
   __shared__ double res[16][4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1087,6 +1138,7 @@ __global__ __launch_bounds__(256) void k_ss_check(const double* __restrict__ Z2,
       worst = v > worst ? v : worst;
     }
     double ref = fabs(theta[0]);
+    *ritz = 1;   // theta holds Ritz values from now on (the filter's tau)
     if (worst <= tol * ref) {
       *done = 1;
       *stat_it = it + 1;
@@ -1380,15 +1432,15 @@ void gemm(const Ctx& c, const double* A, uint32_t lda, const double* B, uint32_t
 // C (s x 64, ld kBlock) = G (s x s) * X (s x n, ld kBlock): split over the
 // summation index when it is long, so that every CU gets a tile.
 void gemm_sq(const Ctx& c, const double* G, uint32_t s, const double* X, double* C, uint32_t n,
-             bool with_done) {
+             bool with_done, Cheb ch = Cheb{0, nullptr, 0, nullptr, nullptr}) {
   const uint32_t nks = s >= 512 ? cdiv(s, kSplitK) : 1;
   // one slice: the kernel's partial layout (rows of 64) is C itself
   double* P = nks > 1 ? c.d(c.SL->skpart) : C;
   hipLaunchKernelGGL(k_gemm_splitk, dim3(cdiv(s, 64), nks), dim3(256), 0, c.st, G, s, X, kBlock, P, s,
-                     s, n, c.stat(with_done));
+                     s, n, ch, c.stat(with_done));
   if (nks > 1)
     hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv((uint64_t)s * 64, 256)), dim3(256), 0, c.st, P, nks,
-                       s, C, kBlock, c.stat(with_done));
+                       s, C, kBlock, X, ch, c.stat(with_done));
 }
 
 void jacobi(const Ctx& c, const double* G, uint32_t nchunk, uint32_t n, double* V, double* lam,
@@ -1455,6 +1507,7 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
   if (b > s) b = s;
   int32_t* tags = c.tags();
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagDone, 0);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c.st, tags + kTagRitz, 0);
   hipLaunchKernelGGL(k_ss_init, dim3(cdiv((uint64_t)s * b, 256)), dim3(256), 0, c.st, Q, kBlock, s,
                      b, tag, tagval, c.stat());
   // Buffers: the Ritz vectors of every Rayleigh-Ritz step go to Qr (so the
@@ -1472,11 +1525,22 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
   };
   double* cur = orthonormalise(c, Q, other(Q, nullptr), s, b, 2, false);
   Status sd = c.stat(true);
+  double* xpair = nullptr;   // input of the current pair of filter steps
   for (int it = 0; it < maxit; ++it) {
     const bool last = it == maxit - 1;
     const bool rr = (it % 8 == 7) || last;
-    double* z = other(cur, nullptr);
-    gemm_sq(c, G, s, cur, z, b, true);
+    // steps come in pairs (a degree-2 Chebyshev filter once Ritz values
+    // exist, plain products before), orthonormalised after the second
+    Cheb ch{it % 2 == 0 ? 1 : 2, lamH, b - 1, tags + kTagRitz, nullptr};
+    double* z;
+    if (it % 2 == 0) {
+      xpair = cur;
+      z = other(cur, nullptr);
+    } else {
+      ch.Xp = xpair;
+      z = other(cur, xpair);
+    }
+    gemm_sq(c, G, s, cur, z, b, true, ch);
     if (!rr) {
       if (it % 2 == 1) z = orthonormalise(c, z, other(z, nullptr), s, b, 1, true);
       cur = z;
@@ -1500,7 +1564,7 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
     gemm(c, z, kBlock, VH, b, Qr, kBlock, s, b, b, true);
     gemm(c, w, kBlock, VH, b, zr, kBlock, s, b, b, true);
     hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, zr, Qr, kBlock, s, lamH, R, 1e-10,
-                       tags + kTagDone, last ? 1 : 0, stat_it, it, c.stat(true));
+                       tags + kTagDone, last ? 1 : 0, stat_it, it, tags + kTagRitz, c.stat(true));
     cur = Qr;
   }
   hipLaunchKernelGGL(k_copy64, dim3(cdiv((uint64_t)s * kBlock, 256)), dim3(256), 0, c.st, Qr, Q,

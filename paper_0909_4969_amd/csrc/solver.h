@@ -52,7 +52,7 @@ constexpr uint32_t kMfmaGramMaxRows = 1024;  // row-side HOSVD Grams on MFMA up 
 // solver statistics at +96 (Jacobi sweeps of the last solve of modes 0..7,
 // +1000 if warm-started; subspace-iteration steps of the HOSVD of modes
 // 0..7 at +128, +10000 if not converged), doubles from +192.
-constexpr int kTagRR = 8, kTagCold = 9, kTagDone = 10;
+constexpr int kTagRR = 8, kTagCold = 9, kTagDone = 10, kTagRitz = 11;
 
 struct SolverLayout {
   size_t status;                         // see above
