@@ -1791,7 +1791,7 @@ hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const So
     jacobi(c, G, 1, s, V, lam, tagc, 0x48000000 | (int32_t)s, false, R);
   } else {
     ldv = kBlock;
-    subspace_topk(c, G, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 96,
+    subspace_topk(c, G, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 48,
                   (int32_t*)(ws + SL.status + 128) + n);
   }
   const uint32_t I = si.dims[n];
