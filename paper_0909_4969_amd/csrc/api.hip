@@ -297,8 +297,9 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
     if (m.contract_mode >= 0) m.ybuf = take((size_t)m.I * m.K * 4);
     else m.ybuf = k < h ? S.TH : S.TT;
     if (m.s <= (uint32_t)kSmallEig) {
-      m.V = take((size_t)m.s * m.s * 8);
-      m.lam = take((size_t)m.s * 8);
+      // eigenbasis (s x s), or the I x 16 block of the short-side iteration
+      m.V = take(std::max((size_t)m.s * m.s, m.kside ? (size_t)m.I * 16 : 0) * 8);
+      m.lam = take((size_t)std::max(m.s, 16u) * 8);
       if (m.kside)
         for (int j = 0; j < d; ++j)
           if (j != k) m.snap[j] = take((size_t)I[j] * 16 * 4);

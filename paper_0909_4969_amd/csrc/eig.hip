@@ -470,6 +470,265 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(ReduceArgs a, Status s) {
   if (lane == 0) a.out[e] = v;
 }
 
+// Column-side mode with a short side (I <= 128, K <= 64, R <= 8): instead
+// of the K x K Gram, the leading left singular vectors of Y_(k) (I x K)
+// come from a block subspace iteration on Y Y^T, with Y held in LDS in
+// float64 and every product on float64 MFMA, in one workgroup:
+//  - start: the previous solve's block of 16 Ritz vectors, else the
+//    current factor A_k (fixed coordinates, so the previous sweep's or the
+//    HOSVD's factor is already close) completed by fixed pseudo-random
+//    columns; two Cholesky-QR passes (the first shifted by 1e-15 tr/16);
+//  - Rayleigh-Ritz on the block (16 x 16 Jacobi from the identity), stop
+//    when the R leading residuals ||Y Y^T q - theta q|| are below 1e-10 of
+//    theta_1;
+//  - else a degree-2 Chebyshev filter on [0, theta_16] (two products by
+//    Y Y^T) and two Cholesky-QR passes, and again.
+// The Ritz vectors are the factor (sign rule as everywhere); theta are the
+// squared singular values (the Gram's eigenvalues).
+constexpr int kSsMaxI = 128, kSsMaxK = 64, kSsB = 16, kSsMaxIt = 8;
+
+struct SsArgs {
+  const float* Y;          // view (O, I, Q) of Y_k: Y_(k)[i][o Q + q] = Y[(o I + i) Q + q]
+  uint32_t O, I, Q, K, R;
+  const double* Aprev;     // I x R, the current factor
+  double* state;           // I x 16: the block of the last solve
+  double* lam;             // >= 16
+  int32_t* tag;
+  int32_t tagval;
+  double* Aout;
+  float* af;
+  int32_t* stats;
+  Status st;
+};
+
+// D (M x N) = op(A) B on float64 MFMA for LDS arrays with leading dims:
+// op(A)[i][k] = TA ? A[k][i] : A[i][k]; M, N multiples of 16, Kd of 4, at
+// most 2 output tiles per wave.  D must not alias A or B.
+template <int NT, bool TA>
+__device__ void ss_mm(const double* A, int lda, const double* Bm, int ldb, double* D, int ldd, int M,
+                      int N, int Kd) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const int tn = N / 16, nt = (M / 16) * tn;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int t = w + u * NW;
+    if (t < nt) {
+      const int ti = t / tn, tj = t % tn;
+      v4d c = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < Kd; k0 += 4) {
+        const int k = k0 + lk, row = ti * 16 + li;
+        const double av = TA ? A[k * lda + row] : A[row * lda + k];
+        const double bv = Bm[k * ldb + tj * 16 + li];
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) D[(ti * 16 + lk + 4 * v) * ldd + tj * 16 + li] = c[v];
+    }
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
+  if (a.st.skip()) return;
+  constexpr int B = kSsB, LB = B + 1, LK = kSsMaxK + 1;
+  __shared__ double Y[kSsMaxI][LK];
+  __shared__ double Q0[kSsMaxI][LB], Q1[kSsMaxI][LB], Q2[kSsMaxI][LB];
+  __shared__ double W[kSsMaxK][LB];
+  __shared__ double S[B][LB];
+  __shared__ double th[B], rinv[B], sgn[B];
+  __shared__ double red[NT / 16][B];
+  __shared__ int col_of_rank[B];
+  __shared__ JacLds<16> J;
+  const int tid = threadIdx.x;
+  const int I = (int)a.I, K = (int)a.K, R = (int)a.R;
+  const int Mp = (I + 15) / 16 * 16, Kp = (K + 15) / 16 * 16;
+  for (int e = tid; e < kSsMaxI * kSsMaxK; e += NT) {
+    const int i = e / kSsMaxK, k = e % kSsMaxK;
+    double v = 0.0;
+    if (i < I && k < K) {
+      const uint32_t o = (uint32_t)k / a.Q, q = (uint32_t)k % a.Q;
+      v = (double)a.Y[((size_t)o * a.I + i) * a.Q + q];
+    }
+    Y[i][k] = v;
+  }
+  const bool warm = *a.tag == a.tagval;
+  for (int e = tid; e < kSsMaxI * B; e += NT) {
+    const int i = e / B, j = e % B;
+    double v = 0.0;
+    if (i < I) {
+      if (warm) v = a.state[i * B + j];
+      else if (j < R) v = a.Aprev[(size_t)i * R + j];
+      else {
+        uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(j + 1) * 0x85EBCA77u;
+        h ^= h >> 15;
+        h *= 0x2C1B3C6Du;
+        h ^= h >> 12;
+        v = (double)(h >> 8) * (1.0 / 16777216.0) - 0.5;
+      }
+    }
+    Q0[i][j] = v;
+  }
+  __syncthreads();
+  double (*Qc)[LB] = Q0, (*Za)[LB] = Q1, (*Zb)[LB] = Q2;
+  // two Cholesky-QR passes on the block P (Mp x 16), in place
+  auto orth = [&](double (*P)[LB]) {
+    for (int pass = 0; pass < 2; ++pass) {
+      ss_mm<NT, true>(&P[0][0], LB, &P[0][0], LB, &S[0][0], LB, B, B, Mp);
+      if (tid < 64) {
+        double tr = tid < B ? S[tid][tid] : 0.0;
+        for (int o = 8; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+        double av[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) av[k] = tid < 16 ? S[tid][k] : 0.0;
+        if (pass == 0)
+#pragma unroll
+          for (int k = 0; k < 16; ++k)
+            if (k == tid) av[k] += 1e-15 * tr / B;
+        chol16_wave(av, tid);
+        if (tid < 16) {
+          double dgl = 1.0;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            S[tid][k] = av[k];
+            if (k == tid) dgl = av[k];
+          }
+          rinv[tid] = 1.0 / dgl;
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < Mp; i += NT) {
+        double q[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double v = P[i][j];
+#pragma unroll
+          for (int k = 0; k < j; ++k) v = fma(-q[k], S[j][k], v);
+          q[j] = v * rinv[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) P[i][j] = q[j];
+      }
+      __syncthreads();
+    }
+  };
+  // D = Y (Y^T P)
+  auto gq = [&](double (*P)[LB], double (*D)[LB]) {
+    ss_mm<NT, true>(&Y[0][0], LK, &P[0][0], LB, &W[0][0], LB, Kp, B, Mp);
+    ss_mm<NT, false>(&Y[0][0], LK, &W[0][0], LB, &D[0][0], LB, Mp, B, Kp);
+  };
+  orth(Qc);
+  bool conv = false;
+  int it = 0;
+  double worst = 0.0, ref = 0.0;
+  for (;; ++it) {
+    // Rayleigh-Ritz: Z = G Q, H = Q^T Z, H = V Theta V^T
+    gq(Qc, Za);
+    ss_mm<NT, true>(&Qc[0][0], LB, &Za[0][0], LB, &J.A[0][0], 17, B, B, Mp);
+    for (int e = tid; e < 16 * 16; e += NT) {
+      const int x = e / 16, y = e % 16;
+      if (x < y) {
+        const double m = 0.5 * (J.A[x][y] + J.A[y][x]);
+        J.A[x][y] = m;
+        J.A[y][x] = m;
+      }
+    }
+    __syncthreads();
+    jacobi_setup<16, NT>(J, 16, false, nullptr);
+    bool jc;
+    jacobi_core<16, NT>(J, 16, R, &jc, 1e-24);
+    jacobi_sort_store<16, NT>(J, 16, nullptr, nullptr);
+    if (tid < 16) col_of_rank[J.rk[tid]] = tid;
+    __syncthreads();
+    if (tid < 16) th[tid] = J.A[col_of_rank[tid]][col_of_rank[tid]];
+    for (int e = tid; e < 16 * 16; e += NT) {   // sorted eigenvectors into J.W
+      const int x = e / 16, r = e % 16;
+      J.W[x][r] = J.V[x][col_of_rank[r]];
+    }
+    __syncthreads();
+    ss_mm<NT, false>(&Qc[0][0], LB, &J.W[0][0], 17, &Zb[0][0], LB, Mp, B, B);   // Ritz vectors
+    ss_mm<NT, false>(&Za[0][0], LB, &J.W[0][0], 17, &Qc[0][0], LB, Mp, B, B);   // G times them
+    {
+      // residuals of the R leading pairs: column r = tid % 16, rows by part
+      const int r = tid % 16, part = tid / 16;
+      double acc = 0.0;
+      if (r < R)
+        for (int i = part; i < Mp; i += NT / 16) {
+          const double d = Qc[i][r] - th[r] * Zb[i][r];
+          acc = fma(d, d, acc);
+        }
+      red[part][r] = acc;
+    }
+    __syncthreads();
+    worst = 0.0;
+    for (int r = 0; r < R; ++r) {
+      double s2 = 0.0;
+      for (int p = 0; p < NT / 16; ++p) s2 += red[p][r];
+      worst = fmax(worst, sqrt(s2));
+    }
+    ref = fabs(th[0]);
+    {
+      double (*t)[LB] = Qc;   // the Ritz vectors become the block
+      Qc = Zb;
+      Zb = t;
+    }
+    conv = worst <= 1e-10 * ref;
+    if (conv || it == kSsMaxIt - 1) break;
+    // degree-2 Chebyshev filter on [0, tau], tau = theta_16 (plain steps if
+    // tau is not a usable bound)
+    const double tau = th[B - 1];
+    const bool cheb = tau > 1e-12 * ref && isfinite(tau);
+    const double a1 = cheb ? 2.0 / tau : 1.0, b1 = cheb ? -1.0 : 0.0;
+    const double a2 = cheb ? 4.0 / tau : 1.0, b2 = cheb ? -2.0 : 0.0, c2 = cheb ? -1.0 : 0.0;
+    gq(Qc, Za);
+    for (int e = tid; e < Mp * B; e += NT) {
+      const int i = e / B, j = e % B;
+      Za[i][j] = a1 * Za[i][j] + b1 * Qc[i][j];
+    }
+    __syncthreads();
+    gq(Za, Zb);
+    for (int e = tid; e < Mp * B; e += NT) {
+      const int i = e / B, j = e % B;
+      Zb[i][j] = a2 * Zb[i][j] + b2 * Za[i][j] + c2 * Qc[i][j];
+    }
+    __syncthreads();
+    {
+      double (*t)[LB] = Qc;
+      Qc = Zb;
+      Zb = t;
+    }
+    orth(Qc);
+  }
+  // sign rule and stores; the block is kept for the next solve
+  if (tid < R) {
+    double best = -1.0, val = 0.0;
+    for (int i = 0; i < I; ++i) {
+      const double v = Qc[i][tid];
+      if (fabs(v) > best) {
+        best = fabs(v);
+        val = v;
+      }
+    }
+    sgn[tid] = val < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < I * 16; e += NT) {
+    const int i = e / 16, r = e % 16;
+    const double v = r < R ? sgn[r] * Qc[i][r] : 0.0;
+    if (r < R) a.Aout[(size_t)i * R + r] = v;
+    a.af[e] = (float)v;
+    a.state[i * B + r] = Qc[i][r];
+  }
+  if (tid < B) a.lam[tid] = th[tid];
+  if (tid == 0) {
+    *a.tag = a.tagval;
+    if (a.stats) *a.stats = 3000 + it + 1;
+    if (!conv && worst > 1e-8 * ref) atomicCAS(a.st.st, 0, MACH_ENOCONV);
+    if (!(th[R - 1] > 1e-13 * th[0])) atomicCAS(a.st.st, 0, MACH_EDEGENERATE);
+  }
+}
+
 // One mode update of a HOOI sweep, sides up to 64, in one workgroup:
 // G = sum of the Gram partials (fixed order); warm-started Jacobi; the
 // eigenpairs sorted and kept for the next sweep.  Row-side Gram: the top R
@@ -694,9 +953,13 @@ __global__ __launch_bounds__(256) void k_chol_apply_tall(double* __restrict__ Aw
     for (int k = 0; k < 16; ++k) a[k] = x < 16 ? S[x][k] : 0.0;
     chol16_wave(a, x);
     if (x < 16) {
+      double dgl = 1.0;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) S[x][k] = a[k];
-      rinv[x] = 1.0 / a[x];
+      for (int k = 0; k < 16; ++k) {
+        S[x][k] = a[k];
+        if (k == x) dgl = a[k];
+      }
+      rinv[x] = 1.0 / dgl;
     }
   }
   __syncthreads();
@@ -1651,6 +1914,27 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
   Ctx c{&SL, ws, hdr, st};
   const ModePlan& m = SL.mp[k];
   int32_t tagval = 0x4d000000 | (k << 16) | (int32_t)m.s;
+  if (m.kside && m.I <= (uint32_t)kSsMaxI && m.K >= (uint32_t)kSsB && m.K <= (uint32_t)kSsMaxK &&
+      m.R <= 8) {
+    SsArgs a;
+    a.Y = (const float*)(ws + m.ybuf);
+    a.O = m.O;
+    a.I = m.I;
+    a.Q = m.Q;
+    a.K = m.K;
+    a.R = m.R;
+    a.Aprev = A_out;
+    a.state = c.d(m.V);
+    a.lam = c.d(m.lam);
+    a.tag = c.tags() + k;
+    a.tagval = tagval;
+    a.Aout = A_out;
+    a.af = (float*)(ws + SL.af[k]);
+    a.stats = (int32_t*)(ws + SL.status + 96) + k;
+    a.st = c.stat();
+    hipLaunchKernelGGL((k_mode_ss<256>), dim3(1), dim3(256), 0, st, a);
+    return hipGetLastError();
+  }
   if (m.s <= (uint32_t)kSmallEig) {
     uint32_t nchunk = 1;
     hipError_t e = launch_gram_y_partials(SL, ws, k, hdr, st, &nchunk);
