@@ -238,9 +238,10 @@ def hosvd(sw: SampleWorkspace, ranks, solver: torch.Tensor, factors=None, stream
 
 def solver_stats(solver: torch.Tensor):
     """Diagnostics kept in the solver workspace (synchronises): per mode,
-    the Jacobi sweeps of its last eigensolve (+1000 when warm-started) and
-    the subspace-iteration steps of its HOSVD eigensolve (+10000 when the
-    residual tolerance was not reached)."""
+    the Jacobi sweeps of its last eigensolve (+1000 when warm-started; 3000 +
+    the Rayleigh-Ritz rounds when the column-side block iteration on Y Y^T
+    ran instead) and the subspace-iteration steps of its HOSVD eigensolve
+    (+10000 when the residual tolerance was not reached)."""
     raw = solver[96:160].view(torch.int32).cpu().tolist()
     return {"jacobi_sweeps": raw[:8], "hosvd_subspace_steps": raw[8:16]}
 

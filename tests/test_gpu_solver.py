@@ -18,6 +18,9 @@ def _w1():
 def _w2():
     X, _ = synth.workload2(shape=(32, 16, 2048), seed=5)
     return X, (8, 4, 16), 0.1, 20262
+def _w2s():
+    X, _ = synth.workload2(shape=(128, 16, 2048), seed=10)
+    return X, (8, 4, 16), 0.1, 20264
 def _w2p01():
     X, _ = synth.workload2(shape=(64, 16, 4096), seed=6)
     return X, (8, 4, 16), 0.01, 20262
@@ -31,7 +34,10 @@ def _big_side():
     X, _ = synth.workload1(shape=(96, 80, 6), ranks=(5, 5, 3), seed=9)
     return X.astype(np.float32), (5, 5, 3), 0.3, 12
 
-CASES = {"tucker-64x32x48-f64": _w1, "monitor-32x16x2048": _w2, "monitor-p0.01-64x16x4096": _w2p01,
+# monitor-128x16x2048: mode 0 has I = 128 > K = 64 with R = 8, the column-side
+# block subspace iteration on Y Y^T
+CASES = {"tucker-64x32x48-f64": _w1, "monitor-32x16x2048": _w2, "monitor-128x16x2048": _w2s,
+         "monitor-p0.01-64x16x4096": _w2p01,
          "voxel-16x16x16x64": _w3, "matrix-300x200": _mat, "sides>64-96x80x6": _big_side}
 
 
@@ -78,6 +84,11 @@ def test_sweeps_one_step_and_end_to_end(name):
         dec.sweep()
         st, _, _ = dec.status()
         assert st == 0, st
+        if name == "monitor-128x16x2048":
+            from paper_0909_4969_amd import mach as M
+            used = M.solver_stats(dec.solver)["jacobi_sweeps"][0]
+            say(f"  sweep {it} mode 0: block iteration, {used - 3000} Rayleigh-Ritz rounds")
+            assert 3000 < used <= 3008, used
         A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_in, ranks)
         for n in range(len(ranks)):
             A_g = dec.factors[n].cpu().numpy()
