@@ -183,14 +183,18 @@ mach_status mach_sample_offsets(const mach_shape* s, uint64_t nnz_cap, uint64_t*
 mach_status mach_read_status(const void* ws_sample, const void* ws_solver, void* stream,
                              int32_t* status_out, uint64_t* nnz_out, double* sumsq_out);
 
-/* Kernel timing for measurement tools.  While enabled, every sparse
- * tensor-times-matrix pass is launched with a start/stop event pair that
- * brackets exactly its dispatch; mach_timing_enable(1) also clears the
- * record.  mach_timing_read waits for the recorded events of one pass kind
- * (which = 0: the pass over head rows, 1: the pass over tail columns) and
- * returns their summed duration in milliseconds and their number.  Events
- * are created once and reused (no device memory).  Not thread safe. */
-mach_status mach_timing_enable(int32_t on);
+/* Kernel timing for measurement tools.  mach_timing_enable(n), n >= 1:
+ * from now on one sparse tensor-times-matrix pass in every n of each kind
+ * (the 1st, (n+1)-th, ...) is launched with a start/stop event pair that
+ * brackets exactly its dispatch; the call also clears the record.  n = 0
+ * turns timing off; n < 0 is MACH_EINVAL.  mach_timing_read waits for the
+ * recorded events of one pass kind (which = 0: the pass over head rows, 1:
+ * the pass over tail columns) and returns their summed duration in
+ * milliseconds and their number.  Events are created once and reused (no
+ * device memory), without a system-scope fence on record, so timing adds
+ * no cache writeback between kernels; sampling 1 in n keeps the markers'
+ * own cost out of the surrounding work.  Not thread safe. */
+mach_status mach_timing_enable(int32_t every);
 mach_status mach_timing_read(int32_t which, double* total_ms, int32_t* count);
 
 /* Static description of a status code. */

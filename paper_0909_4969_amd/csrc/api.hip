@@ -375,22 +375,25 @@ namespace {
 
 // Kernel timing hook state (host side, not thread safe).
 struct TimingPool {
-  bool on = false;
+  int every = 0;                         // 0: off; n: one pass of each kind in every n
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
   size_t used[2] = {0, 0};
+  uint64_t seen[2] = {0, 0};
 };
 TimingPool g_timing;
 
 }  // namespace
 
 bool timing_events(int which, hipEvent_t* e0, hipEvent_t* e1) {
-  if (!g_timing.on || which < 0 || which > 1) return false;
+  if (g_timing.every <= 0 || which < 0 || which > 1) return false;
+  if (g_timing.seen[which]++ % (uint64_t)g_timing.every != 0) return false;
   auto& v = g_timing.ev[which];
   size_t& u = g_timing.used[which];
   if (u == v.size()) {
+    // timing only: no system-scope fence (no cache writeback) at each record
     hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess) return false;
-    if (hipEventCreate(&b) != hipSuccess) {
+    if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
       (void)hipEventDestroy(a);
       return false;
     }
@@ -572,9 +575,11 @@ mach_status mach_core(const void* ws_sample, uint64_t nnz_cap, const mach_shape*
   return ok ? MACH_OK : MACH_EDEVICE;
 }
 
-mach_status mach_timing_enable(int32_t on) {
-  g_timing.on = on != 0;
+mach_status mach_timing_enable(int32_t every) {
+  if (every < 0) return MACH_EINVAL;
+  g_timing.every = every;
   g_timing.used[0] = g_timing.used[1] = 0;
+  g_timing.seen[0] = g_timing.seen[1] = 0;
   return MACH_OK;
 }
 

@@ -131,8 +131,9 @@ def host_selftest() -> int:
     return int(LIB.mach_host_selftest())
 
 
-def timing_enable(on: bool):
-    _check("mach_timing_enable", LIB.mach_timing_enable(1 if on else 0))
+def timing_enable(every: int):
+    """Time one sparse pass in every `every` of each kind (0: off)."""
+    _check("mach_timing_enable", LIB.mach_timing_enable(int(every)))
 
 
 def timing_read(which: int):

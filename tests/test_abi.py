@@ -83,3 +83,15 @@ def test_sample_offsets_are_disjoint_and_aligned(M):
     assert all(o % 256 == 0 for o in offs)
     assert len(set(offs)) == 6
     assert offs[-1] < M.sample_workspace_bytes(shape, cap)
+
+
+def test_timing_hook_host_side(M):
+    """Sampling choice of the kernel timing hook (host state only)."""
+    import ctypes as C
+    assert M.LIB.mach_timing_enable(-1) == M.MACH_EINVAL
+    assert M.LIB.mach_timing_enable(10) == M.MACH_OK
+    ms, n = C.c_double(-1.0), C.c_int32(-1)
+    assert M.LIB.mach_timing_read(0, C.byref(ms), C.byref(n)) == M.MACH_OK
+    assert n.value == 0 and ms.value == 0.0
+    assert M.LIB.mach_timing_read(2, C.byref(ms), C.byref(n)) == M.MACH_EINVAL
+    assert M.LIB.mach_timing_enable(0) == M.MACH_OK
