@@ -160,7 +160,7 @@ inline uint32_t gram_slices(GramArgs& a, size_t part_elems) {
   uint32_t tiles = (a.X + 63) / 64;
   uint64_t n2 = (uint64_t)a.X * a.X;
   uint32_t nchunk = 1;
-  while (nchunk < 64 && (uint64_t)tiles * tiles * nchunk < 512 &&
+  while (nchunk < 256 && (uint64_t)tiles * tiles * nchunk < 512 &&
          a.Z / (2 * nchunk) >= 32 && n2 * (2 * nchunk) <= part_elems)
     nchunk *= 2;
   a.zchunk = (a.Z + nchunk - 1) / nchunk;
