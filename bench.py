@@ -78,7 +78,7 @@ def pmc_summary(fetch_dir, write_dir, copy_mib):
         acc = {}
         for r in rows:
             n = r["Kernel_Name"]
-            m = re.search(r"k_spc<(\d), (\d+), (\d+), (\d), (\d)>", n)
+            m = re.search(r"k_spc<(\d), (\d+), (\d+), (\d), (\d)(?:, \d)?>", n)
             key = None
             if m and m.group(5) == "0":      # float32 factors (the timed path)
                 key = "ttm_tail_cols" if m.group(4) == "1" else "ttm_head_rows"

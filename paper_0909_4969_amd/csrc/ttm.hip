@@ -32,6 +32,7 @@ struct SpcArgs {
   const void* Ain;         // inner factor, row stride 16, zero padded (float32 or bfloat16)
   const void* Aout;        // outer factor (two contracted modes only)
   uint32_t Rin, Rout;
+  uint32_t nin, nout;      // rows of Ain and Aout
   float* out;              // out[seg * K + kappa]
   uint32_t K;
   int G;                   // lanes per segment (power of two, 1..256)
@@ -63,12 +64,33 @@ __device__ __forceinline__ float4 factor4(const void* A, size_t row, int quad) {
   }
 }
 
-template <int NQ, int RI, int RO, int CSC, int BF>
+// LF = 1: the factors are small enough to be copied into LDS (as float32,
+// the RI / 4 and RO / 4 used quads of each row) when the kernel starts, and
+// every factor row is then read from there instead of gathered through L2.
+constexpr uint32_t kLdsFactorBytes = 16384;
+
+template <int NQ, int RI, int RO>
+__host__ __device__ constexpr uint32_t lds_factor_bytes(uint32_t nin, uint32_t nout) {
+  return (nin * (RI / 4) + (NQ == 2 ? nout * (RO / 4) : 0u)) * 16u;
+}
+
+template <int NQ, int RI, int RO, int CSC, int BF, int LF>
 __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
   if (a.hdr->status != 0 || *a.st_solver != 0) return;
   constexpr int LPE = RI / 4;
   static_assert(LPE == 1 || LPE == 2 || LPE == 4, "RI must be 4, 8 or 16");
   __shared__ uint64_t stage[kStage];
+  extern __shared__ float4 fsh[];   // LF: Ain rows (LPE quads each), then Aout rows (RO / 4 quads)
+  if constexpr (LF) {
+    const uint32_t nq_in = a.nin * LPE;
+    for (uint32_t e = threadIdx.x; e < nq_in; e += 256) fsh[e] = factor4<BF>(a.Ain, e / LPE, e % LPE);
+    if constexpr (NQ == 2)
+      for (uint32_t e = threadIdx.x; e < a.nout * (RO / 4); e += 256)
+        fsh[nq_in + e] = factor4<BF>(a.Aout, e / (RO / 4), e % (RO / 4));
+    __syncthreads();
+  }
+  const float4* fin = fsh;
+  const float4* fout = fsh + a.nin * LPE;
   const int G = a.G;
   const int S = G / LPE;
   const int gl = threadIdx.x & (G - 1);
@@ -157,7 +179,7 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
           iin = a.inner_is_lo ? l : h;
           io[u] = ok ? (a.inner_is_lo ? h : l) : 0xffffffffu;
         }
-        w[u] = factor4<BF>(a.Ain, iin, quad);
+        w[u] = LF ? fin[iin * LPE + quad] : factor4<BF>(a.Ain, iin, quad);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -165,7 +187,7 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
           if (cur != 0xffffffffu) {
 #pragma unroll
             for (int o4 = 0; o4 < RO / 4; ++o4) {
-              const float4 wo = factor4<BF>(a.Aout, cur, o4);
+              const float4 wo = LF ? fout[cur * (RO / 4) + o4] : factor4<BF>(a.Aout, cur, o4);
               const float wv[4] = {wo.x, wo.y, wo.z, wo.w};
 #pragma unroll
               for (int oo = 0; oo < 4; ++oo) {
@@ -191,7 +213,7 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
     if (cur != 0xffffffffu) {
 #pragma unroll
       for (int o4 = 0; o4 < RO / 4; ++o4) {
-        const float4 wo = factor4<BF>(a.Aout, cur, o4);
+        const float4 wo = LF ? fout[cur * (RO / 4) + o4] : factor4<BF>(a.Aout, cur, o4);
         const float wv[4] = {wo.x, wo.y, wo.z, wo.w};
 #pragma unroll
         for (int oo = 0; oo < 4; ++oo) {
@@ -242,16 +264,24 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
 
 inline int pad4(uint32_t r) { return r <= 4 ? 4 : r <= 8 ? 8 : r <= 12 ? 12 : 16; }
 
-template <int NQ, int RI, int RO, int CSC, int BF>
-hipError_t go_c(const SpcArgs& a, hipStream_t st) {
+template <int NQ, int RI, int RO, int CSC, int BF, int LF>
+hipError_t go_l(const SpcArgs& a, hipStream_t st) {
   uint32_t per = 256u / a.G;
   dim3 grid((a.nseg + per - 1) / per);
+  const uint32_t lds = LF ? lds_factor_bytes<NQ, RI, RO>(a.nin, a.nout) : 0u;
   hipEvent_t e0, e1;
   if (timing_events(CSC, &e0, &e1))
-    hipExtLaunchKernelGGL((k_spc<NQ, RI, RO, CSC, BF>), grid, dim3(256), 0, st, e0, e1, 0, a);
+    hipExtLaunchKernelGGL((k_spc<NQ, RI, RO, CSC, BF, LF>), grid, dim3(256), lds, st, e0, e1, 0, a);
   else
-    hipLaunchKernelGGL((k_spc<NQ, RI, RO, CSC, BF>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_spc<NQ, RI, RO, CSC, BF, LF>), grid, dim3(256), lds, st, a);
   return hipGetLastError();
+}
+
+template <int NQ, int RI, int RO, int CSC, int BF>
+hipError_t go_c(const SpcArgs& a, hipStream_t st) {
+  if (lds_factor_bytes<NQ, RI, RO>(a.nin, a.nout) <= kLdsFactorBytes)
+    return go_l<NQ, RI, RO, CSC, BF, 1>(a, st);
+  return go_l<NQ, RI, RO, CSC, BF, 0>(a, st);
 }
 
 template <int NQ, int RI, int RO, int BF>
@@ -409,15 +439,18 @@ hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const
   int q = si.d - si.h;
   a.Ain = (const void*)(ws + fac[si.d - 1]);
   a.Rin = ranks[si.d - 1];
+  a.nin = si.dims[si.d - 1];
   if (q == 2) {
     a.flo = si.fdim[si.d - 1];
     a.inner_is_lo = 1;
     a.Aout = (const void*)(ws + fac[si.h]);
     a.Rout = ranks[si.h];
+    a.nout = si.dims[si.h];
   } else {
     a.flo = make_fastdiv(1);
     a.Aout = a.Ain;
     a.Rout = 1;
+    a.nout = 0;
   }
   a.out = (float*)(ws + SL.TH);
   a.K = SL.KT;
@@ -450,14 +483,18 @@ hipError_t launch_contract_head(const ShapeInfo& si, const SparsePtrs& sp, const
     a.inner_is_lo = inner == 1;
     a.Ain = (const void*)(ws + fac[inner]);
     a.Rin = ranks[inner];
+    a.nin = si.dims[inner];
     a.Aout = (const void*)(ws + fac[outer]);
     a.Rout = ranks[outer];
+    a.nout = si.dims[outer];
   } else {
     a.flo = make_fastdiv(1);
     a.Ain = (const void*)(ws + fac[0]);
     a.Rin = ranks[0];
-      a.Aout = a.Ain;
+    a.nin = si.dims[0];
+    a.Aout = a.Ain;
     a.Rout = 1;
+    a.nout = 0;
   }
   a.out = (float*)(ws + SL.TT);
   a.K = SL.KH;
