@@ -309,6 +309,22 @@ def main():
     phase = {name: ev[i].elapsed_time(ev[i + 1]) for i, name in
              enumerate(("sample_ms", "hosvd_ms", "sweeps_ms", "core_ms"))}
     phase["sweep_ms"] = phase["sweeps_ms"] / sweeps
+    # The coin toss + layouts with stream (tick-keyed) coins against window
+    # coins on the same window, 10 calls each (not part of the timed region).
+    coin_ms = {}
+    for kind in ("window", "ticks"):
+        ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev2[0].record()
+        for i in range(10):
+            if kind == "ticks":
+                dec.sample(X, args.seed, 0, tick0=1_000_000 + 997 * i)
+            else:
+                dec.sample(X, args.seed, 1000 + i)
+        ev2[1].record()
+        torch.cuda.synchronize()
+        coin_ms[kind] = ev2[0].elapsed_time(ev2[1]) / 10
+    if dec.status()[0] != 0:
+        raise SystemExit("device status after the coin comparison")
     nnz_w, KT, KH = dec.status()[1], ranks[2], ranks[0] * ranks[1]
     MH, MT = shape[0] * shape[1], shape[2]
 
@@ -344,6 +360,11 @@ def main():
                    "eigensolve_dtype": "f64"},
         "wall_s_timed": round(wall, 3),
         "phases_ms": {k: round(v, 3) for k, v in phase.items()},
+        "stream_coins": {"sample_ms_window_coins": round(coin_ms["window"], 4),
+                         "sample_ms_tick_coins": round(coin_ms["ticks"], 4),
+                         "input_GBs_tick_coins": round(X.numel() * 4 / (coin_ms["ticks"] / 1e3) / 1e9, 1),
+                         "note": "coin toss + compaction + layouts of the window; tick coins "
+                                 "keyed on (seed, series, absolute tick)"},
         "sweep_only_nnz_per_s": round(nnz / (phase["sweep_ms"] / 1e3), 1),
         "roofline": roofline,
     }

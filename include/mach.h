@@ -99,6 +99,22 @@ mach_status mach_sample(const mach_shape* s, mach_dtype x_dtype, const void* X_d
                         double p, uint64_t seed, uint64_t window_id,
                         void* ws, size_t ws_bytes, uint64_t nnz_cap, void* stream);
 
+/* The coin toss for windows of a stream (Remark 2: a coin per measurement as
+ * it arrives, so that windows which share measurements share their coins).
+ * The last mode of s is time: X_dev holds ticks tick0 .. tick0 + I_d - 1 of
+ * the series indexed by the other modes.  Entry (j, t), j the C-order flat
+ * index of the other coordinates, is kept iff word (tau mod 4) of the
+ * Philox4x32-10 block at counter (q lo, q hi, j, 0), q = tau / 4,
+ * tau = tick0 + t, key (seed lo, seed hi), is below T (as for mach_sample).
+ * The coin of a measurement thus depends on its series, its absolute tick
+ * and the seed only: two windows of the same series layout that overlap in
+ * time keep exactly the same measurements in the overlap.  Workspace,
+ * outputs, errors and every later call are as for mach_sample;
+ * tick0 + I_d must not exceed 2^64 (MACH_EINVAL). */
+mach_status mach_sample_ticks(const mach_shape* s, mach_dtype x_dtype, const void* X_dev, double p,
+                              uint64_t seed, uint64_t tick0, void* ws, size_t ws_bytes,
+                              uint64_t nnz_cap, void* stream);
+
 /* Bytes of the solver workspace for shape s and ranks R_1..R_d (host array
  * of d int32).  prec is the sparse-TTM factor precision mach_hooi_sweep
  * will be called with (MACH_F32 or MACH_BF16; the workspace serves both).

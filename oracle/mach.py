@@ -29,6 +29,11 @@ Readings where the paper is silent or ambiguous (each listed in the design doc):
       sweeps is run and the fit is reported after every sweep.
   R6  Norm invariance (eq. eqa) holds for U with orthonormal columns
       (U^T U = I); the paper writes U U^T = I.
+  R9  Streams (Remark 2: a coin as each measurement arrives): for a window
+      whose last mode is time, the coin of a measurement is keyed by (seed,
+      series, absolute tick) -- Philox4x32-10 at counter (tick/4 lo, tick/4
+      hi, series, 0), word tick mod 4 -- so every window that contains the
+      measurement draws the same coin (oracle/philox.py, mask_words_ticks).
 
 Parity status: every function below is pinned by tests/test_oracle_*.py,
 except `theorem1_hypotheses` (report-only: its conditions are checked, the
@@ -41,7 +46,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .philox import mask_words
+from .philox import mask_words, mask_words_ticks
 
 # ---------------------------------------------------------------------------
 # Sampling (Theorem 1; Remark 1; Alg. 1 and Alg. 2, "MACH" block)
@@ -68,6 +73,39 @@ def sample_mask(shape, p: float, seed: int, window_id: int) -> np.ndarray:
         lin = np.arange(s, min(n, s + step), dtype=np.uint64)
         out[s:s + lin.size] = mask_words(lin, seed, window_id).astype(np.uint64) < np.uint64(T)
     return out.reshape(shape)
+
+
+def sample_mask_ticks(shape, p: float, seed: int, tick0: int) -> np.ndarray:
+    """Boolean keep-mask of a window of a stream (reading R9): the last mode
+    is time, holding ticks tick0 .. tick0 + shape[-1] - 1; the coin of entry
+    (series j, tick tau) depends on (seed, j, tau) only."""
+    T = int(shape[-1])
+    nser = int(np.prod(shape[:-1]))
+    thr = np.uint64(keep_threshold(p))
+    out = np.empty((nser, T), dtype=bool)
+    ticks = np.uint64(tick0) + np.arange(T, dtype=np.uint64)
+    step = max(1, (1 << 22) // T)
+    for j0 in range(0, nser, step):
+        js = np.arange(j0, min(nser, j0 + step), dtype=np.uint64)[:, None]
+        out[j0:j0 + js.shape[0]] = mask_words_ticks(js, ticks[None, :], seed).astype(np.uint64) < thr
+    return out.reshape(shape)
+
+
+def sample_coo_ticks(X: np.ndarray, p: float, seed: int, tick0: int) -> SampledCOO:
+    """The coin toss of a stream window with tick-keyed coins, as a COO list."""
+    if X.size >= (1 << 32):
+        raise ValueError("linear indices must fit in 32 bits")
+    mask = sample_mask_ticks(X.shape, p, seed, tick0).ravel()
+    idx = np.flatnonzero(mask).astype(np.uint32)
+    x = X.ravel()[idx]
+    return SampledCOO(tuple(X.shape), p, idx, x.astype(np.float32),
+                      float(np.sum(x.astype(np.float64) ** 2)))
+
+
+def sampled_tensor_ticks(X: np.ndarray, p: float, seed: int, tick0: int) -> np.ndarray:
+    """Dense X-hat of a stream window under tick-keyed coins (float64)."""
+    mask = sample_mask_ticks(X.shape, p, seed, tick0)
+    return np.where(mask, X.astype(np.float64) / p, 0.0)
 
 
 @dataclass

@@ -99,3 +99,25 @@ def mask_words(lin, seed, window_id):
     sel = (lin & np.uint64(3)).astype(np.int64)
     stacked = np.stack(outs, axis=0)
     return np.take_along_axis(stacked, sel[None, ...], axis=0)[0]
+
+
+def mask_words_ticks(series, tick, seed):
+    """The 32-bit word of a measurement of series `series` at absolute tick
+    `tick` (uint64 arrays that broadcast together) under tick-keyed coins.
+
+    Counter layout (this build's reading for streams, Remark 2):
+        counter = (q mod 2^32, q >> 32, series, 0), q = tick // 4
+        key     = (seed mod 2^32, seed >> 32)
+        word    = output word number (tick mod 4) of that block.
+    """
+    series = np.asarray(series, dtype=np.uint64)
+    tick = np.asarray(tick, dtype=np.uint64)
+    series, tick = np.broadcast_arrays(series, tick)
+    q = tick >> np.uint64(2)
+    s = np.uint64(seed)
+    m32 = np.uint64(0xFFFFFFFF)
+    outs = philox4x32_10(q & m32, q >> np.uint64(32), series & m32, np.zeros_like(q),
+                         s & m32, s >> np.uint64(32))
+    sel = (tick & np.uint64(3)).astype(np.int64)
+    stacked = np.stack(outs, axis=0)
+    return np.take_along_axis(stacked, sel[None, ...], axis=0)[0]

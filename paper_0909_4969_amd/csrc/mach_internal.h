@@ -75,10 +75,11 @@ struct SampleHdr {
   double p;
   double sumsq;          // sum of kept x^2 (unscaled)
   uint64_t thresh;       // keep iff word < thresh
-  uint64_t seed, window;
+  uint64_t seed, window;  // window: the window id, or the first tick (tick-keyed coins)
   int32_t status;
   int32_t magic;
-  uint64_t pad[7];
+  uint64_t coin;         // 0: coins keyed by (seed, window) on l; 1: by (seed, series, tick)
+  uint64_t pad[6];
 };
 constexpr int32_t kSampleMagic = 0x4d414348;   // "MACH"
 
@@ -113,6 +114,6 @@ __device__ __forceinline__ uint32_t bit_rank(const uint64_t* bitmap, const uint3
 // ---------------------------------------------------------------------------
 hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, double p,
                          uint64_t seed, uint64_t window, char* ws, const SampleLayout& L,
-                         uint64_t cap, hipStream_t st);
+                         uint64_t cap, hipStream_t st, int coin = 0);
 
 }  // namespace mach

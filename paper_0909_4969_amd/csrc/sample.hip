@@ -81,8 +81,9 @@ __device__ __forceinline__ uint32_t block_exscan256(uint32_t v, uint32_t* sh, ui
 }
 
 __global__ void k_sample_init(SampleHdr* hdr, double p, uint64_t thresh, uint64_t cap,
-                              uint64_t seed, uint64_t window) {
+                              uint64_t seed, uint64_t window, uint64_t coin) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    hdr->coin = coin;
     hdr->nnz = 0;
     hdr->cap = cap;
     hdr->p = p;
@@ -114,6 +115,57 @@ __global__ __launch_bounds__(kThreads) void k_sample_mask(uint32_t N, uint64_t t
         uint32_t l = l0 + 4u * j + k;
         uint64_t keep = ((uint64_t)c[k] < thresh) && (l < N);
         bits |= keep << (4 * j + k);
+      }
+    }
+  }
+  bitmap[w] = bits;
+  uint32_t tot = block_sum256<uint32_t>((uint32_t)__popcll(bits), sh);
+  if (threadIdx.x == 0) blkcnt[blockIdx.x] = tot;
+}
+
+// Tick-keyed coins for a window of consecutive ticks of a stream: the last
+// mode is time, entry l = j T + t (j the series, the flat index of the other
+// coordinates; t the tick within the window) gets word tau mod 4 of the
+// Philox block at counter (q lo, q hi, j, 0), q = tau / 4, tau = tick0 + t,
+// key (seed lo, seed hi).  A measurement gets the same coin in every window
+// that contains it.  One thread per 64-bit bitmap word; a block is computed
+// once for the (up to four) consecutive ticks that share it.
+__global__ __launch_bounds__(kThreads) void k_sample_mask_ticks(uint32_t N, FastDiv fT, uint64_t thresh,
+                                                                uint32_t s_lo, uint32_t s_hi,
+                                                                uint64_t tick0,
+                                                                uint64_t* __restrict__ bitmap,
+                                                                uint32_t* __restrict__ blkcnt) {
+  __shared__ uint32_t sh[4];
+  const uint32_t w = blockIdx.x * kSampleBlockWords + threadIdx.x;
+  uint64_t bits = 0;
+  const uint32_t l0 = w * 64u;
+  if (l0 < N) {
+    uint32_t j = fT.div(l0), t = l0 - j * fT.d;
+    uint64_t tau = tick0 + t;
+    uint32_t c[4] = {0u, 0u, 0u, 0u};
+    uint64_t cq = ~0ull;
+    uint32_t cj = ~0u;
+    const uint32_t nb = min(64u, N - l0);
+    for (uint32_t b = 0; b < nb; ++b) {
+      const uint64_t q = tau >> 2;
+      if (q != cq || j != cj) {
+        c[0] = (uint32_t)q;
+        c[1] = (uint32_t)(q >> 32);
+        c[2] = j;
+        c[3] = 0u;
+        philox4x32_10(c, s_lo, s_hi);
+        cq = q;
+        cj = j;
+      }
+      const uint32_t sel = (uint32_t)tau & 3u;
+      const uint32_t word = sel == 0 ? c[0] : sel == 1 ? c[1] : sel == 2 ? c[2] : c[3];
+      bits |= (uint64_t)((uint64_t)word < thresh) << b;
+      if (++t == fT.d) {
+        t = 0;
+        ++j;
+        tau = tick0;
+      } else {
+        ++tau;
       }
     }
   }
@@ -361,7 +413,7 @@ __global__ __launch_bounds__(256) void k_csc_fill(ShapeInfo si, const uint64_t* 
 
 hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, double p, uint64_t seed,
                          uint64_t window, char* ws, const SampleLayout& L, uint64_t cap,
-                         hipStream_t st) {
+                         hipStream_t st, int coin) {
   SampleHdr* hdr = (SampleHdr*)(ws + L.hdr);
   uint64_t* bitmap = (uint64_t*)(ws + L.bitmap);
   uint32_t* wrank = (uint32_t*)(ws + L.wrank);
@@ -377,10 +429,16 @@ hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, doubl
   uint64_t thresh = (uint64_t)std::floor(p * 4294967296.0);
   if (thresh > (1ull << 32)) thresh = 1ull << 32;
 
-  hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, hdr, p, thresh, cap, seed, window);
-  hipLaunchKernelGGL(k_sample_mask, dim3(si.nblk), dim3(kThreads), 0, st, si.N, thresh,
-                     (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)window,
-                     (uint32_t)(window >> 32), bitmap, blkcnt);
+  hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, hdr, p, thresh, cap, seed, window,
+                     (uint64_t)coin);
+  if (coin)
+    hipLaunchKernelGGL(k_sample_mask_ticks, dim3(si.nblk), dim3(kThreads), 0, st, si.N,
+                       si.fdim[si.d - 1], thresh, (uint32_t)seed, (uint32_t)(seed >> 32), window,
+                       bitmap, blkcnt);
+  else
+    hipLaunchKernelGGL(k_sample_mask, dim3(si.nblk), dim3(kThreads), 0, st, si.N, thresh,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)window,
+                       (uint32_t)(window >> 32), bitmap, blkcnt);
   scan_u32(blkcnt, si.nblk, (uint32_t*)(ws + L.scan_tmp), st);
   if (x_is_f64)
     hipLaunchKernelGGL(k_sample_compact<double>, dim3(si.nblk), dim3(kThreads), 0, st,

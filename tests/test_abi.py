@@ -95,3 +95,19 @@ def test_timing_hook_host_side(M):
     assert n.value == 0 and ms.value == 0.0
     assert M.LIB.mach_timing_read(2, C.byref(ms), C.byref(n)) == M.MACH_EINVAL
     assert M.LIB.mach_timing_enable(0) == M.MACH_OK
+
+
+def test_sample_ticks_rejects_wrapping_ticks(M):
+    """Host-side argument checks of mach_sample_ticks (no launch happens)."""
+    import ctypes as C
+    shape = (4, 8)
+    s = M.Shape.of(shape)
+    cap = M.nnz_capacity(shape, 0.5)
+    fake = C.c_void_p(1 << 20)          # aligned; never dereferenced on these paths
+    nb = M.sample_workspace_bytes(shape, cap)
+    rc = M.LIB.mach_sample_ticks(C.byref(s), M.MACH_F32, fake, 0.5, 1, (1 << 64) - 4, fake, nb, cap, None)
+    assert rc == M.MACH_EINVAL
+    rc = M.LIB.mach_sample_ticks(C.byref(s), M.MACH_F32, fake, 1.5, 1, 0, fake, nb, cap, None)
+    assert rc == M.MACH_EINVAL
+    rc = M.LIB.mach_sample_ticks(C.byref(s), M.MACH_F32, fake, 0.5, 1, 0, fake, nb - 1, cap, None)
+    assert rc == M.MACH_ENOMEM

@@ -118,3 +118,81 @@ def test_full_size_monitoring_tensor_sampled_positions():
     np.testing.assert_array_equal(sw.u32("colptr", MT + 1), colptr)
     tidx, _ = sw.entries("coo_t", nnz)
     np.testing.assert_array_equal(tidx, idx[order])
+
+
+TICK_CASES = [
+    ("ticks-128x16x2048", (128, 16, 2048), "f32", 0.1, 5, 1000003),      # T a multiple of 64
+    ("ticks-7x5x333", (7, 5, 333), "f32", 0.3, 6, 2**32 + 1),            # ragged T, high tick word
+    ("ticks-64x100", (64, 100), "f64", 0.5, 7, 0),
+    ("ticks-4x4x4x97", (4, 4, 4, 97), "f32", 0.2, 2**63 + 9, 2),
+]
+
+
+@pytest.mark.parametrize("name,shape,dt,p,seed,tick0", TICK_CASES, ids=[c[0] for c in TICK_CASES])
+def test_tick_keyed_sample_bit_exact(name, shape, dt, p, seed, tick0):
+    """mach_sample_ticks against the oracle's tick-keyed coins (reading R9):
+    bitmap, COO and the layouts built from them, bit for bit."""
+    import torch
+    from paper_0909_4969_amd import mach as M
+    X = _input(shape, dt, seed % 1000)
+    coo = O.sample_coo_ticks(X, p, seed, tick0)
+    say("sample ticks", name, shape, p, tick0)
+    sw = M.sample(torch.from_numpy(X).cuda(), p, seed, 0, tick0=tick0)
+    st, nnz, ss = sw.status()
+    assert st == 0
+    assert nnz == coo.nnz
+    idx, val = sw.entries("coo_l", nnz)
+    np.testing.assert_array_equal(idx, coo.idx)
+    np.testing.assert_array_equal(val.view(np.uint32), coo.val.view(np.uint32))
+    assert abs(ss - coo.sumsq) <= 1e-12 * max(coo.sumsq, 1e-300)
+    N = int(np.prod(shape))
+    nwords = ((N + 16383) // 16384) * 256
+    words = sw.u64("bitmap", nwords)
+    np.testing.assert_array_equal(words, pack_mask(O.sample_mask_ticks(shape, p, seed, tick0).ravel(), nwords))
+    h, perm = M.layout_info(shape)
+    MH = int(np.prod(shape[:h]))
+    np.testing.assert_array_equal(sw.u32("rowptr", MH + 1), S.row_pointers(coo.idx, shape, h))
+
+
+def test_overlapping_stream_windows_keep_the_same_measurements():
+    """Two windows of one stream that overlap in time keep exactly the same
+    measurements (and values) in the overlap."""
+    import torch
+    from paper_0909_4969_amd import mach as M
+    rng = np.random.default_rng(8)
+    series = rng.standard_normal((16, 8, 1800)).astype(np.float32)   # ticks 500 .. 2299
+    T, t0a, t0b, p, seed = 1024, 500, 884, 0.1, 42
+    kept = []
+    for t0 in (t0a, t0b):
+        Xw = np.ascontiguousarray(series[..., t0 - 500:t0 - 500 + T])
+        say("sample window ticks", t0)
+        sw = M.sample(torch.from_numpy(Xw).cuda(), p, seed, 0, tick0=t0)
+        st, nnz, _ = sw.status()
+        assert st == 0
+        idx, val = sw.entries("coo_l", nnz)
+        j, t = idx.astype(np.int64) // T, idx.astype(np.int64) % T
+        kept.append({(int(a), int(b) + t0): v for a, b, v in zip(j, t, val.view(np.uint32))})
+    lo, hi = t0b, t0a + T
+    ov = [{k: v for k, v in d.items() if lo <= k[1] < hi} for d in kept]
+    assert len(ov[0]) > 1000
+    assert ov[0] == ov[1]
+
+
+def test_tick_keyed_window_through_hosvd():
+    """The solver on a tick-keyed sample matches the oracle's HOSVD of the
+    same sampled tensor."""
+    import torch
+    from paper_0909_4969_amd import mach as M
+    from tests.gpu_helpers import subspace_tol
+    X, _ = synth.workload2(shape=(32, 16, 2048), seed=12)
+    ranks, p, seed, t0 = (8, 4, 16), 0.1, 99, 123457
+    dec = M.Decomposition(X.shape, ranks, p)
+    say("hosvd on tick-keyed sample")
+    dec.sample(torch.from_numpy(X).cuda(), seed, 0, tick0=t0)
+    dec.hosvd()
+    assert dec.status()[0] == 0
+    Xh = O.sampled_tensor_ticks(X, p, seed, t0)
+    for n, A_o in enumerate(O.hosvd_factors(Xh, ranks)):
+        Un = O.unfold(Xh, n)
+        tol = subspace_tol(O.eigengap(Un, ranks[n]), O.davis_kahan_bound(Un, ranks[n], 2.0**-24))
+        assert O.sin_theta(A_o, dec.factors[n].cpu().numpy()) <= tol
