@@ -573,7 +573,7 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   __syncthreads();
   double (*Qc)[LB] = Q0, (*Za)[LB] = Q1, (*Zb)[LB] = Q2;
   // two Cholesky-QR passes on the block P (Mp x 16), in place
-  auto orth = [&](double (*P)[LB]) {
+  auto orth = [&](double (*P)[LB]) __attribute__((always_inline)) {
     for (int pass = 0; pass < 2; ++pass) {
       ss_mm<NT, true>(&P[0][0], LB, &P[0][0], LB, &S[0][0], LB, B, B, Mp);
       if (tid < 64) {
@@ -614,11 +614,43 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
     }
   };
   // D = Y (Y^T P)
-  auto gq = [&](double (*P)[LB], double (*D)[LB]) {
+  auto gq = [&](double (*P)[LB], double (*D)[LB]) __attribute__((always_inline)) {
     ss_mm<NT, true>(&Y[0][0], LK, &P[0][0], LB, &W[0][0], LB, Kp, B, Mp);
     ss_mm<NT, false>(&Y[0][0], LK, &W[0][0], LB, &D[0][0], LB, Mp, B, Kp);
   };
+  // degree-2 Chebyshev filter on [0, tau] applied to the block Qc, then two
+  // Cholesky-QR passes (plain steps if tau is not a usable bound)
+  auto filter = [&](double tau, double ref) __attribute__((always_inline)) {
+    const bool cheb = tau > 1e-12 * ref && isfinite(tau);
+    const double a1 = cheb ? 2.0 / tau : 1.0, b1 = cheb ? -1.0 : 0.0;
+    const double a2 = cheb ? 4.0 / tau : 1.0, b2 = cheb ? -2.0 : 0.0, c2 = cheb ? -1.0 : 0.0;
+    gq(Qc, Za);
+    for (int e = tid; e < Mp * B; e += NT) {
+      const int i = e / B, j = e % B;
+      Za[i][j] = a1 * Za[i][j] + b1 * Qc[i][j];
+    }
+    __syncthreads();
+    gq(Za, Zb);
+    for (int e = tid; e < Mp * B; e += NT) {
+      const int i = e / B, j = e % B;
+      Zb[i][j] = a2 * Zb[i][j] + b2 * Za[i][j] + c2 * Qc[i][j];
+    }
+    __syncthreads();
+    {
+      double (*t)[LB] = Qc;
+      Qc = Zb;
+      Zb = t;
+    }
+    orth(Qc);
+  };
   orth(Qc);
+  // Warm: the previous block is Ritz vectors of the previous matrix, so the
+  // filter (on the previous theta_16) goes first and the first Rayleigh-Ritz
+  // step already sees the filtered block.
+  if (warm) {
+    const double tau0 = a.lam[B - 1], ref0 = a.lam[0];
+    if (tau0 > 1e-12 * ref0 && isfinite(tau0)) filter(tau0, ref0);
+  }
   bool conv = false;
   int it = 0;
   double worst = 0.0, ref = 0.0;
@@ -675,30 +707,7 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
     }
     conv = worst <= 1e-10 * ref;
     if (conv || it == kSsMaxIt - 1) break;
-    // degree-2 Chebyshev filter on [0, tau], tau = theta_16 (plain steps if
-    // tau is not a usable bound)
-    const double tau = th[B - 1];
-    const bool cheb = tau > 1e-12 * ref && isfinite(tau);
-    const double a1 = cheb ? 2.0 / tau : 1.0, b1 = cheb ? -1.0 : 0.0;
-    const double a2 = cheb ? 4.0 / tau : 1.0, b2 = cheb ? -2.0 : 0.0, c2 = cheb ? -1.0 : 0.0;
-    gq(Qc, Za);
-    for (int e = tid; e < Mp * B; e += NT) {
-      const int i = e / B, j = e % B;
-      Za[i][j] = a1 * Za[i][j] + b1 * Qc[i][j];
-    }
-    __syncthreads();
-    gq(Za, Zb);
-    for (int e = tid; e < Mp * B; e += NT) {
-      const int i = e / B, j = e % B;
-      Zb[i][j] = a2 * Zb[i][j] + b2 * Za[i][j] + c2 * Qc[i][j];
-    }
-    __syncthreads();
-    {
-      double (*t)[LB] = Qc;
-      Qc = Zb;
-      Zb = t;
-    }
-    orth(Qc);
+    filter(th[B - 1], ref);   // tau = theta_16
   }
   // sign rule and stores; the block is kept for the next solve
   if (tid < R) {
