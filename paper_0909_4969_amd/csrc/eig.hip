@@ -544,31 +544,50 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   const int tid = threadIdx.x;
   const int I = (int)a.I, K = (int)a.K, R = (int)a.R;
   const int Mp = (I + 15) / 16 * 16, Kp = (K + 15) / 16 * 16;
-  for (int e = tid; e < kSsMaxI * kSsMaxK; e += NT) {
-    const int i = e / kSsMaxK, k = e % kSsMaxK;
-    double v = 0.0;
-    if (i < I && k < K) {
-      const uint32_t o = (uint32_t)k / a.Q, q = (uint32_t)k % a.Q;
-      v = (double)a.Y[((size_t)o * a.I + i) * a.Q + q];
-    }
-    Y[i][k] = v;
-  }
-  const bool warm = *a.tag == a.tagval;
-  for (int e = tid; e < kSsMaxI * B; e += NT) {
-    const int i = e / B, j = e % B;
-    double v = 0.0;
-    if (i < I) {
-      if (warm) v = a.state[i * B + j];
-      else if (j < R) v = a.Aprev[(size_t)i * R + j];
-      else {
-        uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(j + 1) * 0x85EBCA77u;
-        h ^= h >> 15;
-        h *= 0x2C1B3C6Du;
-        h ^= h >> 12;
-        v = (double)(h >> 8) * (1.0 / 16777216.0) - 0.5;
+  // eight loads per thread issued before their LDS stores
+  static_assert(kSsMaxI * kSsMaxK % (8 * NT) == 0, "Y load in groups of eight");
+  for (int e0 = 0; e0 < kSsMaxI * kSsMaxK; e0 += 8 * NT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT + tid, i = e / kSsMaxK, k = e % kSsMaxK;
+      v[u] = 0.0f;
+      if (i < I && k < K) {
+        const uint32_t o = (uint32_t)k / a.Q, q = (uint32_t)k % a.Q;
+        v[u] = a.Y[((size_t)o * a.I + i) * a.Q + q];
       }
     }
-    Q0[i][j] = v;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT + tid;
+      Y[e / kSsMaxK][e % kSsMaxK] = (double)v[u];
+    }
+  }
+  const bool warm = *a.tag == a.tagval;
+  static_assert(kSsMaxI * B == 8 * NT, "start block loaded as eight values per thread");
+  {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = u * NT + tid, i = e / B, j = e % B;
+      v[u] = 0.0;
+      if (i < I) {
+        if (warm) v[u] = a.state[i * B + j];
+        else if (j < R) v[u] = a.Aprev[(size_t)i * R + j];
+        else {
+          uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(j + 1) * 0x85EBCA77u;
+          h ^= h >> 15;
+          h *= 0x2C1B3C6Du;
+          h ^= h >> 12;
+          v[u] = (double)(h >> 8) * (1.0 / 16777216.0) - 0.5;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = u * NT + tid;
+      Q0[e / B][e % B] = v[u];
+    }
   }
   __syncthreads();
   double (*Qc)[LB] = Q0, (*Za)[LB] = Q1, (*Zb)[LB] = Q2;
@@ -643,10 +662,10 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
     }
     orth(Qc);
   };
-  orth(Qc);
-  // Warm: the previous block is Ritz vectors of the previous matrix, so the
-  // filter (on the previous theta_16) goes first and the first Rayleigh-Ritz
-  // step already sees the filtered block.
+  // Warm: the previous block holds orthonormal Ritz vectors of the previous
+  // matrix, so the filter (on the previous theta_16) goes first and the
+  // first Rayleigh-Ritz step already sees the filtered block.
+  if (!warm) orth(Qc);
   if (warm) {
     const double tau0 = a.lam[B - 1], ref0 = a.lam[0];
     if (tau0 > 1e-12 * ref0 && isfinite(tau0)) filter(tau0, ref0);
