@@ -474,10 +474,12 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(ReduceArgs a, Status s) {
 // of the K x K Gram, the leading left singular vectors of Y_(k) (I x K)
 // come from a block subspace iteration on Y Y^T, with Y held in LDS in
 // float64 and every product on float64 MFMA, in one workgroup:
-//  - start: the previous solve's block of 16 Ritz vectors, else the
-//    current factor A_k (fixed coordinates, so the previous sweep's or the
-//    HOSVD's factor is already close) completed by fixed pseudo-random
-//    columns; two Cholesky-QR passes (the first shifted by 1e-15 tr/16);
+//  - start: the previous solve's block of 16 orthonormal Ritz vectors,
+//    passed once through the filter below on the previous theta_16; else
+//    the current factor A_k (fixed coordinates, so the previous sweep's or
+//    the HOSVD's factor is already close) completed by fixed pseudo-random
+//    columns and made orthonormal by two Cholesky-QR passes (the first
+//    shifted by 1e-15 tr/16);
 //  - Rayleigh-Ritz on the block (16 x 16 Jacobi from the identity), stop
 //    when the R leading residuals ||Y Y^T q - theta q|| are below 1e-10 of
 //    theta_1;
