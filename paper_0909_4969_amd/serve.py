@@ -36,13 +36,17 @@ from . import mach as M
 
 @dataclass
 class Window:
-    """One request: a device-resident float32 window of one stream."""
+    """One request: a device-resident float32 window of one stream.  With
+    tick0 (the absolute tick of the window's first time step) the coins are
+    keyed on (seed, series, tick), so windows of a stream that overlap in time
+    keep the same measurements; else on (seed, window_id, position)."""
     req_id: int
     stream_id: int
     window_id: int
     arrival_s: float
     X: torch.Tensor
     seed: int
+    tick0: int | None = None
 
 
 @dataclass
@@ -131,7 +135,7 @@ class Engine:
             fit = torch.zeros(1, dtype=torch.float64, device=self.device)
             G = torch.empty(tuple(cfg.ranks), dtype=torch.float64, device=self.device)
             norm2 = torch.empty(1, dtype=torch.float64, device=self.device)
-            M.sample(win.X, cfg.p, win.seed, win.window_id, ws=sw, stream=s)
+            M.sample(win.X, cfg.p, win.seed, win.window_id, ws=sw, stream=s, tick0=win.tick0)
             if warm:
                 factors = [res[1][0].clone(), res[1][1].clone(),
                            torch.zeros(shape[2], cfg.ranks[2], dtype=torch.float64, device=self.device)]
