@@ -195,16 +195,21 @@ hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream
 // Column-side Gram of the sampled unfolding when the mode is the single
 // tail mode: G[r][r'] = sum_c Xhat[r, c] Xhat[r', c] over the CSR rows r
 // (head rows) and tail columns c.  The CSC columns list their entries in
-// the head order of the CSC layout (position headpos[r]), so the entries
-// of column c at or after row r in that order start at the entry (r, c)
-// itself, whose CSC position the layout build recorded (cscpos).  One wave per row r walks the row's
-// entries (c, v) in order; for each, its lanes take those entries (r', v')
-// of column c and add v v' to a float64 accumulator of row r in LDS.  The
-// entries of one column have distinct r', so lanes never collide, and every
-// accumulator is summed in column order.  Row r writes G[r][r'] for
-// headpos[r'] >= headpos[r]; k_gram_mirror fills the rest by symmetry.
-// Row r = v / 2 for even wave index v and MH - 1 - v / 2 for odd v, so every
-// workgroup holds long and short rows alike.
+// the head order of the CSC layout (position headpos[r]); the entry (r, c)
+// itself sits at the CSC position the layout build recorded (cscpos).  Each
+// pair of entries of a column is taken once, by one of its two rows: in an
+// even column by the row that comes first in head order (the entries from
+// (r, c) to the column's end), in an odd column by the row that comes last
+// (the entries from the column's start to (r, c)).  Every row then does
+// about the same work, half a column per entry, wherever it sits in head
+// order.  One wave per row r walks the row's entries (c, v) in order; for
+// each, its lanes take the entries (r', v') of its part of column c and add
+// v v' to a float64 accumulator of row r in LDS.  The entries of one column
+// have distinct r', so lanes never collide, and every accumulator is summed
+// in column order.  Row r writes its whole accumulator row: G[r][r'] then
+// holds the even columns' sum when r comes first, the odd columns' sum when
+// r comes last, and k_gram_mirror adds the two halves of every pair.
+// Row r = v / 2 for even wave index v and MH - 1 - v / 2 for odd v.
 constexpr uint32_t kSparseGramMaxRows = 2048;
 
 __global__ __launch_bounds__(256) void k_gram_rows_sparse(uint32_t MH, FastDiv fMT,
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(256) void k_gram_rows_sparse(uint32_t MH, FastDiv f
   for (uint32_t j = lane; j < MH; j += 64) row[j] = 0.0;
   __builtin_amdgcn_wave_barrier();
   if (v < MH) {
-    const uint32_t base = r * fMT.d, pr = headpos[r];
+    const uint32_t base = r * fMT.d;
     const uint32_t e1 = rowptr[r + 1];
     for (uint32_t e0 = rowptr[r]; e0 < e1; e0 += 64) {
       // lane i holds the descriptor of entry e0 + i: value, first and end
@@ -235,9 +240,15 @@ __global__ __launch_bounds__(256) void k_gram_rows_sparse(uint32_t MH, FastDiv f
       float va = 0.0f;
       if (e < e1) {
         const Entry a = coo_l[e];
+        const uint32_t c = a.l - base;
         va = a.v;
         lo = cscpos[e];
-        hi = colptr[a.l - base + 1];
+        if (c & 1u) {
+          hi = lo + 1;
+          lo = colptr[c];
+        } else {
+          hi = colptr[c + 1];
+        }
       }
       const int cnt = (int)min(64u, e1 - e0);
       for (int k = 0; k < cnt; k += 4) {
@@ -265,13 +276,15 @@ __global__ __launch_bounds__(256) void k_gram_rows_sparse(uint32_t MH, FastDiv f
       }
     }
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t j = lane; j < MH; j += 64)
-      if (headpos[j] >= pr) G[(size_t)r * MH + j] = row[j];
+    for (uint32_t j = lane; j < MH; j += 64) G[(size_t)r * MH + j] = row[j];
   }
 }
 
-// The entries G[x][y] with headpos[y] < headpos[x] from their transposes,
-// by pairs of 64 x 64 tiles (bi, bj) and (bj, bi), bi >= bj, through LDS.
+// Completes the Gram left by k_gram_rows_sparse: for x before y in head
+// order G[x][y] holds the even columns' sum and G[y][x] the odd columns';
+// both become their sum, added in that order (so the result is exactly
+// symmetric).  The diagonal is already whole.  By pairs of 64 x 64 tiles
+// (bi, bj) and (bj, bi), bi >= bj, through LDS.
 __global__ __launch_bounds__(256) void k_gram_mirror(uint32_t MH, const uint32_t* __restrict__ headpos,
                                                      double* __restrict__ G, const SampleHdr* hdr,
                                                      const int32_t* st_solver) {
@@ -295,9 +308,15 @@ __global__ __launch_bounds__(256) void k_gram_mirror(uint32_t MH, const uint32_t
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const uint32_t x = e >> 6, y = e & 63;
     const uint32_t ar = bi * 64 + x, ac = bj * 64 + y;
-    if (ar < MH && ac < MH && pj[y] < pi_[x]) G[(size_t)ar * MH + ac] = tb[y][x];
+    if (ar < MH && ac < MH && ar != ac) {
+      const double own = ta[x][y], tr = tb[y][x];
+      G[(size_t)ar * MH + ac] = pi_[x] < pj[y] ? own + tr : tr + own;
+    }
     const uint32_t br = bj * 64 + x, bc = bi * 64 + y;
-    if (bi != bj && br < MH && bc < MH && pi_[y] < pj[x]) G[(size_t)br * MH + bc] = ta[y][x];
+    if (bi != bj && br < MH && bc < MH) {
+      const double own = tb[x][y], tr = ta[y][x];
+      G[(size_t)br * MH + bc] = pj[x] < pi_[y] ? own + tr : tr + own;
+    }
   }
 }
 
