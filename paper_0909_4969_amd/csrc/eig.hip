@@ -2037,7 +2037,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     if (m.s <= 16)
       hipLaunchKernelGGL((k_mode_solve<16, 256>), dim3(1), dim3(256), 0, st, a);
     else if (m.s <= 32)
-      hipLaunchKernelGGL((k_mode_solve<32, 256>), dim3(1), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_mode_solve<32, 512>), dim3(1), dim3(512), 0, st, a);
     else
       hipLaunchKernelGGL((k_mode_solve<64, 1024>), dim3(1), dim3(1024), 0, st, a);
     if (m.kside) {
