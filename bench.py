@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "sampled nnz/s per HOOI sweep + p50/p99 window latency, mixed-prec vs FP32"
 HBM_PEAK_GBS = 8000.0
 TIMING_EVERY = 10      # timed sparse passes: one in every 10 of each kind
+PHASE_WINDOWS = 5      # extra windows for the per-phase averages
 
 
 def parse():
@@ -293,21 +294,27 @@ def main():
     cols_ms, cols_n = M.timing_read(1)
     M.timing_enable(0)
 
-    # Per-phase times of one extra step (not part of the timed region).
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-    ev[0].record()
-    dec.sample(X, args.seed, 999)
-    ev[1].record()
-    dec.hosvd()
-    ev[2].record()
-    for _ in range(sweeps):
-        dec.sweep()
-    ev[3].record()
-    dec.core()
-    ev[4].record()
-    torch.cuda.synchronize()
-    phase = {name: ev[i].elapsed_time(ev[i + 1]) for i, name in
-             enumerate(("sample_ms", "hosvd_ms", "sweeps_ms", "core_ms"))}
+    # Per-phase times, averaged over PHASE_WINDOWS extra windows (not part of
+    # the timed region; the sweep time varies from window to window).
+    names = ("sample_ms", "hosvd_ms", "sweeps_ms", "core_ms")
+    per = {k: [] for k in names}
+    for wi in range(PHASE_WINDOWS):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
+        dec.sample(X, args.seed, 1000 + wi)
+        ev[1].record()
+        dec.hosvd()
+        ev[2].record()
+        for _ in range(sweeps):
+            dec.sweep()
+        ev[3].record()
+        dec.core()
+        ev[4].record()
+        torch.cuda.synchronize()
+        for i, k in enumerate(names):
+            per[k].append(ev[i].elapsed_time(ev[i + 1]))
+    phase = {k: sum(v) / len(v) for k, v in per.items()}
+    phase_range = {k: [round(min(v), 3), round(max(v), 3)] for k, v in per.items()}
     phase["sweep_ms"] = phase["sweeps_ms"] / sweeps
     # The coin toss + layouts with stream (tick-keyed) coins against window
     # coins on the same window, 10 calls each (not part of the timed region).
@@ -360,6 +367,8 @@ def main():
                    "eigensolve_dtype": "f64"},
         "wall_s_timed": round(wall, 3),
         "phases_ms": {k: round(v, 3) for k, v in phase.items()},
+        "phases_ms_range": phase_range,
+        "phases_windows": PHASE_WINDOWS,
         "stream_coins": {"sample_ms_window_coins": round(coin_ms["window"], 4),
                          "sample_ms_tick_coins": round(coin_ms["ticks"], 4),
                          "input_GBs_tick_coins": round(X.numel() * 4 / (coin_ms["ticks"] / 1e3) / 1e9, 1),
@@ -369,10 +378,12 @@ def main():
         "roofline": roofline,
     }
     # Mixed precision on the same window: 20 sweeps after HOSVD with bfloat16
-    # factor entries in the sparse TTM, against the float32 run above.
+    # factor entries in the sparse TTM, against the float32 run of the last
+    # per-phase window above.
     A32 = [a.clone() for a in dec.factors]
     fit32 = float(dec.fit.item())
-    dec.sample(X, args.seed, 999)
+    last_win = 1000 + PHASE_WINDOWS - 1
+    dec.sample(X, args.seed, last_win)
     dec.hosvd()
     torch.cuda.synchronize()
     eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -389,7 +400,8 @@ def main():
         a32, abf = a32.cpu().numpy(), abf.cpu().numpy()
         sin_max = max(sin_max, float(np.linalg.norm(abf - a32 @ (a32.T @ abf), 2)))
     out["precision"] = {
-        "f32": {"sweep_ms": round(phase["sweep_ms"], 4), "fit": fit32},
+        "window": last_win,
+        "f32": {"sweep_ms": round(per["sweeps_ms"][-1] / sweeps, 4), "fit": fit32},
         "bf16": {"sweep_ms": round(eb0.elapsed_time(eb1) / sweeps, 4), "fit": float(dec.fit.item()),
                  "max_sin_theta_vs_f32": sin_max},
         "note": "bf16 = sparse-TTM factor entries rounded to bfloat16, float32 sums, float64 eigensolve",
