@@ -483,8 +483,8 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(ReduceArgs a, Status s) {
 //  - Rayleigh-Ritz on the block (16 x 16 Jacobi from the identity), stop
 //    when the R leading residuals ||Y Y^T q - theta q|| are below 1e-10 of
 //    theta_1;
-//  - else a degree-2 Chebyshev filter on [0, theta_16] (two products by
-//    Y Y^T) and two Cholesky-QR passes, and again.
+//  - else twice a degree-2 Chebyshev filter on [0, theta_16] (two products
+//    by Y Y^T, then two Cholesky-QR passes), and again.
 // The Ritz vectors are the factor (sign rule as everywhere); theta are the
 // squared singular values (the Gram's eigenvalues).
 constexpr int kSsMaxI = 128, kSsMaxK = 64, kSsB = 16, kSsMaxIt = 8;
@@ -733,7 +733,10 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
     }
     conv = worst <= 1e-10 * ref;
     if (conv || it == kSsMaxIt - 1) break;
-    filter(th[B - 1], ref);   // tau = theta_16
+    // tau = theta_16; two applications between Rayleigh-Ritz steps (one
+    // seldom sufficed, and the step between would not change the span)
+    filter(th[B - 1], ref);
+    filter(th[B - 1], ref);
   }
   // sign rule and stores; the block is kept for the next solve
   if (tid < R) {
