@@ -237,7 +237,7 @@ def main():
         print(json.dumps(d))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU sharding is a design, not built)"}))
         sys.exit(2)
     import torch

@@ -55,7 +55,7 @@ typedef int32_t mach_status;
 #define MACH_EINVAL       -1  /* an argument is out of range                    */
 #define MACH_ENOMEM       -2  /* workspace too small, or kept count > capacity  */
 #define MACH_EDEVICE      -3  /* a HIP runtime call failed                      */
-#define MACH_EUNSUPPORTED -4  /* valid input this build does not handle         */
+#define MACH_EUNSUPPORTED -4  /* valid input the library does not handle         */
 #define MACH_EDEGENERATE  -5  /* a Gram matrix has rank below R_n               */
 #define MACH_ENOCONV      -6  /* eigensolver residual tolerance not reached     */
 

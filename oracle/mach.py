@@ -16,7 +16,7 @@ and algorithms:
   * Theorem 1 and Remark 1: the sampled tensor keeps X/p with probability p.
   * Algorithm 1 (MACH-HOSVD) and Algorithm 2 (MACH-HOOI).
 
-Readings where the paper is silent or ambiguous (each listed in the design doc):
+Readings where the paper is silent or ambiguous:
   R1  Factors come from the sampled tensor X-hat (Alg. 1), not X.
   R2  One coin per entry, zero entries included; the coin is Philox4x32-10
       keyed by (seed, window) on the C-order linear index (oracle/philox.py);

@@ -8,9 +8,9 @@ random numbers: as easy as 1, 2, 3", SC'11, Section 3.3 (the Philox
 S-box: two multiplications, a hi/lo split and an xor with the round key)
 and Section 3.3's constants table.
 
-The paper being implemented (MACH) only says "toss a coin with probability
-p of keeping it" for every entry (Alg. 1 and Alg. 2, the MACH comment
-block; Remark 1).  It names no generator.  This build reads that as one
+The paper being implemented (MACH) keeps each entry with probability p by
+an independent coin toss (Alg. 1 and Alg. 2, the MACH comment block;
+Remark 1) and names no generator.  The reading taken here is one
 independent Bernoulli(p) draw per linear index, produced by Philox4x32-10
 keyed by (seed, window); see `mask_words` for the counter layout.
 
@@ -84,7 +84,7 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
 def mask_words(lin, seed, window_id):
     """The 32-bit random word attached to each linear index `lin` (uint64 array).
 
-    Counter layout (this build's reading; the paper fixes none):
+    Counter layout (the reading taken here; the paper fixes none):
         counter = (q mod 2^32, q >> 32, window mod 2^32, window >> 32), q = lin // 4
         key     = (seed mod 2^32, seed >> 32)
         word    = output word number (lin mod 4) of that block.
@@ -105,7 +105,7 @@ def mask_words_ticks(series, tick, seed):
     """The 32-bit word of a measurement of series `series` at absolute tick
     `tick` (uint64 arrays that broadcast together) under tick-keyed coins.
 
-    Counter layout (this build's reading for streams, Remark 2):
+    Counter layout (the reading taken here for streams, Remark 2):
         counter = (q mod 2^32, q >> 32, series, 0), q = tick // 4
         key     = (seed mod 2^32, seed >> 32)
         word    = output word number (tick mod 4) of that block.

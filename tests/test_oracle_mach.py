@@ -264,7 +264,7 @@ def test_planted_dropped_mode_is_caught(monkeypatch, small_problem):
 
 def test_harmonic_tensor_qualitative():
     """Section 4's synthetic tensor x_ijk = 1/(i+j+k), rank (4,4,4), p = 0.1.
-    The printed core values and 87% accuracy do not reproduce (see DESIGN.md);
+    The printed core values and 87% accuracy do not reproduce from the garbled table;
     what does: g(1,1,1) dominates the exact core, and the leading MACH
     components correlate with the exact ones (rho >= 0.99 per mode)."""
     n, r = 200, 4
