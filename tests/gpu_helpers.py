@@ -42,3 +42,42 @@ def rel(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# Measures applied to what the device returned.  They never go through the
+# oracle: the oracle only ever sees host inputs and its own results.
+
+def sin_theta(A_ref, A):
+    """Sine of the largest principal angle between span(A_ref) and span(A),
+    ||(I - A_ref A_ref^T) A||_2, for orthonormal bases."""
+    A_ref = np.asarray(A_ref, np.float64)
+    A = np.asarray(A, np.float64)
+    P = A - A_ref @ (A_ref.T @ A)
+    return float(np.linalg.norm(P, 2)) if P.size else 0.0
+
+
+def project(T, factors):
+    """T x_1 A_1^T x_2 ... x_d A_d^T in float64 (the mode products spelled
+    out with tensordot; mode n of the result has size R_n)."""
+    R = np.asarray(T, np.float64)
+    for n, A in enumerate(factors):
+        R = np.moveaxis(np.tensordot(np.asarray(A, np.float64), R, axes=(0, n)), 0, n)
+    return R
+
+
+def recon_rel_error(X, G, factors):
+    """||X - G x_n A_n|| / ||X|| for orthonormal factors, from
+    ||X||^2 - 2 <X x_n A_n^T, G> + ||G||^2."""
+    X = np.asarray(X, np.float64)
+    G = np.asarray(G, np.float64)
+    nx2 = float(np.sum(X * X))
+    val = nx2 - 2.0 * float(np.sum(project(X, factors) * G)) + float(np.sum(G * G))
+    return math.sqrt(max(0.0, val) / nx2)
+
+
+def load_factors(dec, factors):
+    """Copies host float64 factors into a decomposition's device factors, so
+    that a device step and an oracle step start from the same input."""
+    import torch
+    for f, a in zip(dec.factors, factors):
+        f.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)))

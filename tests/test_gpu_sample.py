@@ -7,7 +7,7 @@ import pytest
 import synth
 from oracle import mach as O
 from oracle import segments as S
-from tests.gpu_helpers import pack_mask, say
+from tests.gpu_helpers import pack_mask, say, sin_theta, subspace_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -183,7 +183,6 @@ def test_tick_keyed_window_through_hosvd():
     same sampled tensor."""
     import torch
     from paper_0909_4969_amd import mach as M
-    from tests.gpu_helpers import subspace_tol
     X, _ = synth.workload2(shape=(32, 16, 2048), seed=12)
     ranks, p, seed, t0 = (8, 4, 16), 0.1, 99, 123457
     dec = M.Decomposition(X.shape, ranks, p)
@@ -195,4 +194,4 @@ def test_tick_keyed_window_through_hosvd():
     for n, A_o in enumerate(O.hosvd_factors(Xh, ranks)):
         Un = O.unfold(Xh, n)
         tol = subspace_tol(O.eigengap(Un, ranks[n]), O.davis_kahan_bound(Un, ranks[n], 2.0**-24))
-        assert O.sin_theta(A_o, dec.factors[n].cpu().numpy()) <= tol
+        assert sin_theta(A_o, dec.factors[n].cpu().numpy()) <= tol
