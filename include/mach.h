@@ -55,7 +55,7 @@ typedef int32_t mach_status;
 #define MACH_EINVAL       -1  /* an argument is out of range                    */
 #define MACH_ENOMEM       -2  /* workspace too small, or kept count > capacity  */
 #define MACH_EDEVICE      -3  /* a HIP runtime call failed                      */
-#define MACH_EUNSUPPORTED -4  /* valid input the library does not handle         */
+#define MACH_EUNSUPPORTED -4  /* valid input the library does not handle        */
 #define MACH_EDEGENERATE  -5  /* a Gram matrix has rank below R_n               */
 #define MACH_ENOCONV      -6  /* eigensolver residual tolerance not reached     */
 
@@ -94,7 +94,11 @@ uint64_t mach_nnz_capacity(const mach_shape* s, double p);
  *            same entries regrouped for the other modes, sum x_l^2 in
  *            float64, and the kept count.
  * Returns MACH_OK or MACH_EINVAL / MACH_ENOMEM / MACH_EUNSUPPORTED /
- * MACH_EDEVICE.  A kept count above nnz_cap sets MACH_ENOMEM on the device. */
+ * MACH_EDEVICE.  On the device (read with mach_read_status): a kept count
+ * above nnz_cap sets MACH_ENOMEM; else a kept value that is not finite sets
+ * MACH_EINVAL; else a sample whose kept values are all zero (none kept, or
+ * X zero there) sets MACH_EDEGENERATE, since every Gram is then zero.  The
+ * layouts are still written; solver calls on such a sample do nothing. */
 mach_status mach_sample(const mach_shape* s, mach_dtype x_dtype, const void* X_dev,
                         double p, uint64_t seed, uint64_t window_id,
                         void* ws, size_t ws_bytes, uint64_t nnz_cap, void* stream);

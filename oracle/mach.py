@@ -34,6 +34,11 @@ Readings where the paper is silent or ambiguous:
       series, absolute tick) -- Philox4x32-10 at counter (tick/4 lo, tick/4
       hi, series, 0), word tick mod 4 -- so every window that contains the
       measurement draws the same coin (oracle/philox.py, mask_words_ticks).
+  R10 A sampled tensor with no nonzero entry (nothing kept, or X zero where
+      kept) has zero matricizations: their leading singular vectors, and so
+      the factors of Alg. 1 and 2, are not determined.  Such a sample is
+      degenerate (DegenerateSample); one with a non-finite entry is rejected
+      (ValueError).
 
 Parity status: every function below is pinned by tests/test_oracle_*.py,
 except `theorem1_hypotheses` (report-only: its conditions are checked, the
@@ -279,8 +284,22 @@ def leading_left_singular_vectors(M: np.ndarray, r: int):
 # ---------------------------------------------------------------------------
 
 
+class DegenerateSample(ValueError):
+    """The sampled tensor is zero, so no factor is determined (reading R10)."""
+
+
+def check_sample(Xh: np.ndarray) -> None:
+    """Reading R10: rejects a sampled tensor with a non-finite entry
+    (ValueError) or with no nonzero entry (DegenerateSample)."""
+    if not np.all(np.isfinite(Xh)):
+        raise ValueError("the sampled tensor has a non-finite entry")
+    if not np.any(Xh):
+        raise DegenerateSample("the sampled tensor is zero")
+
+
 def hosvd_factors(Xh: np.ndarray, ranks):
     """A^(i) = r_i leading left singular vectors of X-hat_(i), i = 1..d (Alg. 1)."""
+    check_sample(Xh)
     return [leading_left_singular_vectors(unfold(Xh, i), ranks[i])[0]
             for i in range(Xh.ndim)]
 
@@ -296,6 +315,7 @@ def hooi_sweep(Xh: np.ndarray, factors, ranks, first_mode: int = 0):
     Returns (new factors, list of ||core||^2 after each mode update).  After
     the update of mode n, ||G||^2 = sum of the top r_n squared singular values
     of Y_(n) (norm invariance, eq. eqa)."""
+    check_sample(Xh)
     A = [np.array(a, dtype=np.float64) for a in factors]
     trace = []
     for n in range(first_mode, Xh.ndim):

@@ -330,7 +330,13 @@ __global__ __launch_bounds__(256) void k_sample_finalize(SampleHdr* hdr, const u
     hdr->nnz = nnz;
     hdr->sumsq = s;
     wrank[nwords] = (uint32_t)nnz;
+    // No kept value other than zero: every Gram of the sampled tensor is
+    // zero and no subspace is determined.  A kept value that is not finite
+    // would poison every product.  Either way the solver calls that follow
+    // on this sample do nothing (their kernels check this status).
     if (nnz > hdr->cap) hdr->status = MACH_ENOMEM;
+    else if (!(s < INFINITY)) hdr->status = MACH_EINVAL;
+    else if (s == 0.0) hdr->status = MACH_EDEGENERATE;
   }
 }
 

@@ -195,3 +195,52 @@ def test_tick_keyed_window_through_hosvd():
         Un = O.unfold(Xh, n)
         tol = subspace_tol(O.eigengap(Un, ranks[n]), O.davis_kahan_bound(Un, ranks[n], 2.0**-24))
         assert sin_theta(A_o, dec.factors[n].cpu().numpy()) <= tol
+
+
+DEGENERATE = [
+    ("empty-6x5x7", 1e-6, 1, "empty"),          # the coins keep nothing
+    ("zero-tensor-6x5x7", 0.5, 2, "zero"),      # kept values are all zero
+    ("nan-kept-6x5x7", 0.5, 3, "nan"),          # a kept value is NaN
+]
+
+
+@pytest.mark.parametrize("name,p,seed,kind", DEGENERATE, ids=[c[0] for c in DEGENERATE])
+def test_degenerate_sample_sets_status_and_solver_does_nothing(name, p, seed, kind):
+    """Reading R10 on the device: the sample reports MACH_EDEGENERATE where
+    the oracle finds the sampled tensor zero, MACH_EINVAL where it finds a
+    non-finite kept value; the layouts are still exact, and HOSVD, a sweep
+    and the core leave the factors and the core untouched."""
+    import torch
+    from paper_0909_4969_amd import mach as M
+    shape, ranks = (6, 5, 7), (2, 2, 2)
+    X = _input(shape, "f32", seed)
+    mask = O.sample_mask(shape, p, seed, 0).ravel()
+    if kind == "zero":
+        X[...] = 0.0
+    if kind == "nan":
+        X.reshape(-1)[np.flatnonzero(mask)[0]] = np.nan
+    with pytest.raises(ValueError) as e:
+        O.hosvd_factors(O.sampled_tensor(X, p, seed, 0), ranks)
+    expect = M.MACH_EINVAL if kind == "nan" else M.MACH_EDEGENERATE
+    assert isinstance(e.value, O.DegenerateSample) == (expect == M.MACH_EDEGENERATE)
+    dec = M.Decomposition(shape, ranks, p)
+    say("degenerate sample", name)
+    dec.sample(torch.from_numpy(X).cuda(), seed, 0)
+    st, nnz, _ = dec.status()
+    assert st == expect, (st, expect)
+    assert nnz == int(mask.sum())
+    coo = O.sample_coo(X, p, seed, 0)
+    idx, _ = dec.sw.entries("coo_l", nnz)
+    np.testing.assert_array_equal(idx, coo.idx)
+    h, _ = M.layout_info(shape)
+    MH = int(np.prod(shape[:h]))
+    np.testing.assert_array_equal(dec.sw.u32("rowptr", MH + 1), S.row_pointers(coo.idx, shape, h))
+    say("solver on degenerate sample", name)
+    dec.hosvd()
+    dec.sweep()
+    dec.core()
+    st, _, _ = dec.status()
+    assert st == expect, (st, expect)
+    for f in dec.factors:
+        assert not bool(f.any())
+    assert not bool(dec.G.any())

@@ -285,3 +285,30 @@ def test_theorem1_conditions_fail_for_workloads():
     for w in (synth.WORKLOADS[1], synth.WORKLOADS[2], synth.WORKLOADS[3]):
         h = O.theorem1_hypotheses(w.shape, w.ps[0])
         assert not h["p_ok"]
+
+
+def test_degenerate_and_non_finite_samples():
+    """Reading R10: with nothing nonzero kept every matricization is zero
+    (all its singular values vanish) and the factors are not determined; a
+    non-finite kept value is rejected; one at a dropped position is not."""
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((6, 5, 7))
+    mask = O.sample_mask(X.shape, 1e-6, 1, 0)
+    assert not mask.any()
+    Xh = O.sampled_tensor(X, 1e-6, 1, 0)
+    assert all(np.linalg.svd(O.unfold(Xh, n), compute_uv=False).max() == 0.0 for n in range(3))
+    with pytest.raises(O.DegenerateSample):
+        O.hosvd_factors(Xh, (2, 2, 2))
+    with pytest.raises(O.DegenerateSample):
+        O.hosvd_factors(O.sampled_tensor(np.zeros_like(X), 0.5, 2, 0), (2, 2, 2))
+    mask = O.sample_mask(X.shape, 0.5, 3, 0).ravel()
+    Xn = X.copy()
+    Xn.ravel()[np.flatnonzero(~mask)[0]] = np.nan          # dropped by the coin
+    Xh = O.sampled_tensor(Xn, 0.5, 3, 0)
+    assert np.all(np.isfinite(Xh))
+    O.hosvd_factors(Xh, (2, 2, 2))
+    Xn.ravel()[np.flatnonzero(mask)[0]] = np.nan           # kept
+    with pytest.raises(ValueError):
+        O.hosvd_factors(O.sampled_tensor(Xn, 0.5, 3, 0), (2, 2, 2))
+    with pytest.raises(ValueError):
+        O.hooi_sweep(O.sampled_tensor(Xn, 0.5, 3, 0), [np.eye(6, 2), np.eye(5, 2), np.eye(7, 2)], (2, 2, 2))
