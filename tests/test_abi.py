@@ -60,6 +60,11 @@ def test_size_queries(M):
     assert M.solver_workspace_bytes((64, 64, 64), (17, 2, 2), 100) == 0
     assert M.solver_workspace_bytes((4, 4, 4, 4, 4), (2, 2, 2, 2, 2), 100) == 0
     assert M.sample_workspace_bytes((4, 0, 4), 10) == 0
+    # the largest tensor: fewer than 2^31 entries (uint32 linear indices with
+    # headroom for the word arithmetic of the coin toss)
+    assert M.sample_workspace_bytes((1024, 1024, 2047), 1 << 20) > 0
+    assert M.sample_workspace_bytes((1024, 1024, 2048), 1 << 20) == 0
+    assert M.nnz_capacity((1024, 1024, 2048), 0.01) == 0
 
 
 def test_layout_choice(M):

@@ -244,3 +244,44 @@ def test_degenerate_sample_sets_status_and_solver_does_nothing(name, p, seed, ki
     for f in dec.factors:
         assert not bool(f.any())
     assert not bool(dec.G.any())
+
+
+def test_maximum_size_sample_sampled_positions():
+    """The largest accepted tensor, 1024 x 1024 x 2047 float32 (2^31 - 2^20
+    entries, 8.6 GB, drawn on the device) at p = 0.01: Binomial kept count,
+    increasing kept indices, and the mask, kept values, sum of squares and
+    column layout against the oracle on sampled windows of the index."""
+    import torch
+    from paper_0909_4969_amd import mach as M
+    shape, p, seed, win = (1024, 1024, 2047), 0.01, 77, 5
+    N = int(np.prod(shape))
+    g = torch.Generator(device="cuda").manual_seed(123)
+    X = torch.randn(shape, generator=g, device="cuda", dtype=torch.float32)
+    say("sample maximum size", shape)
+    sw = M.sample(X, p, seed, win)
+    st, nnz, ss = sw.status()
+    assert st == 0, st
+    q = O.keep_threshold(p) / 2**32
+    assert abs(nnz - N * q) < 6 * math.sqrt(N * q * (1 - q))
+    idx, val = sw.entries("coo_l", nnz)
+    assert np.all(np.diff(idx.astype(np.int64)) > 0)
+    flat = X.view(-1)
+    kept_x = flat[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy()
+    np.testing.assert_array_equal(val.view(np.uint32), kept_x.view(np.uint32))
+    assert abs(ss - float(np.sum(kept_x.astype(np.float64) ** 2))) <= 1e-10 * ss
+    rng = np.random.default_rng(2)
+    starts = [0, N - 65536] + [int(s) for s in rng.integers(0, N - 65536, 6)]
+    for lo in starts:
+        hi = lo + 65536
+        lin = np.arange(lo, hi, dtype=np.uint64)
+        keep = O.mask_words(lin, seed, win).astype(np.uint64) < np.uint64(O.keep_threshold(p))
+        want = np.flatnonzero(keep).astype(np.int64) + lo
+        sel = (idx >= lo) & (idx < hi)
+        np.testing.assert_array_equal(idx[sel].astype(np.int64), want)
+    h, perm = M.layout_info(shape)
+    MH = int(np.prod(shape[:h]))
+    order, colptr = S.column_order(idx, shape, h, perm)
+    np.testing.assert_array_equal(sw.u32("colptr", N // MH + 1), colptr)
+    np.testing.assert_array_equal(sw.u32("rowptr", MH + 1), S.row_pointers(idx, shape, h))
+    tidx, _ = sw.entries("coo_t", nnz)
+    np.testing.assert_array_equal(tidx, idx[order])
