@@ -90,6 +90,8 @@ def pmc_summary(fetch_dir, write_dir, copy_mib):
         return {k: sum(v) / len(v) for k, v in acc.items()}
 
     fetch, write = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+    # the counter runs' output folders, relative to the repository root ($R)
+    fd, wd = os.path.relpath(fetch_dir, ROOT), os.path.relpath(write_dir, ROOT)
     true_bytes = copy_mib * (1 << 20)
     f_scale = true_bytes / (fetch["copy"] * 1024.0)
     w_scale = true_bytes / (write["copy"] * 1024.0)
@@ -102,10 +104,10 @@ def pmc_summary(fetch_dir, write_dir, copy_mib):
                                 for k in ("ttm_head_rows", "ttm_tail_cols")},
            "commands": [
                "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE "
-               "--output-format csv -d $R/gpurun_out/pmc_fetch -o run -- python3 $R/bench.py --steps 1 "
-               "--warmup 1 --no-cpu-baseline --serve-requests 0 --copy-mib 1024",
-               "(the same with --pmc WRITE_SIZE and -d $R/gpurun_out/pmc_write)",
-               "python3 bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write --copy-mib 1024"]}
+               f"--output-format csv -d $R/{fd} -o run -- python3 $R/bench.py --steps 1 "
+               f"--warmup 1 --no-cpu-baseline --serve-requests 0 --copy-mib {copy_mib}",
+               f"(the same with --pmc WRITE_SIZE and -d $R/{wd})",
+               f"python3 bench.py --pmc-summary {fd} {wd} --copy-mib {copy_mib}"]}
     return out
 
 
