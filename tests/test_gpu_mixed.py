@@ -13,7 +13,7 @@ import pytest
 
 from oracle import mach as O
 from tests.gpu_helpers import load_factors, project, recon_rel_error, say, sin_theta
-from tests.test_gpu_solver import CASES, _setup
+from tests.test_gpu_solver import _setup
 
 pytestmark = pytest.mark.gpu
 
