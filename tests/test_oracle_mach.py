@@ -312,3 +312,34 @@ def test_degenerate_and_non_finite_samples():
         O.hosvd_factors(O.sampled_tensor(Xn, 0.5, 3, 0), (2, 2, 2))
     with pytest.raises(ValueError):
         O.hooi_sweep(O.sampled_tensor(Xn, 0.5, 3, 0), [np.eye(6, 2), np.eye(5, 2), np.eye(7, 2)], (2, 2, 2))
+
+
+def test_fit_from_norms_is_the_residual_of_the_projection():
+    """fit_from_norms(||Xhat||^2, ||G||^2) equals 1 - ||Xhat - G x A|| / ||Xhat||
+    with the reconstruction written out (orthonormal factors, eq. eqa)."""
+    rng = np.random.default_rng(8)
+    Xh = rng.standard_normal((9, 7, 8))
+    A = [np.linalg.qr(rng.standard_normal((s, r)))[0] for s, r in zip(Xh.shape, (3, 2, 4))]
+    G = np.einsum("ijk,ia,jb,kc->abc", Xh, *A)
+    R = np.einsum("abc,ia,jb,kc->ijk", G, *A)
+    direct = 1.0 - np.linalg.norm(Xh - R) / np.linalg.norm(Xh)
+    assert O.fit_from_norms(float(np.sum(Xh ** 2)), float(np.sum(G ** 2))) == pytest.approx(direct, abs=1e-12)
+    assert O.fit_from_norms(4.0, 4.0) == 1.0 and O.fit_from_norms(4.0, 0.0) == 0.0
+
+
+def test_eigengap_and_davis_kahan_closed_forms():
+    """On a matrix with prescribed singular values s: the relative gap is
+    (s_r^2 - s_{r+1}^2) / s_1^2 and the bound 4 u sum s^2 / (s_r^2 - s_{r+1}^2);
+    a repeated s_r gives a zero gap."""
+    rng = np.random.default_rng(9)
+    s = np.array([5.0, 4.0, 2.0, 1.0, 0.5])
+    U = np.linalg.qr(rng.standard_normal((8, 5)))[0]
+    V = np.linalg.qr(rng.standard_normal((6, 5)))[0]
+    Mx = U @ np.diag(s) @ V.T
+    for r in (1, 2, 3):
+        gap = s[r - 1] ** 2 - s[r] ** 2
+        assert O.eigengap(Mx, r) == pytest.approx(gap / s[0] ** 2, rel=1e-12)
+        assert O.davis_kahan_bound(Mx, r, 2.0 ** -24) == pytest.approx(4 * 2.0 ** -24 * np.sum(s ** 2) / gap, rel=1e-12)
+    Mt = U @ np.diag([3.0, 3.0, 1.0, 1.0, 1.0]) @ V.T
+    assert O.eigengap(Mt, 1) == pytest.approx(0.0, abs=1e-14)
+    assert O.eigengap(Mx, 5) == pytest.approx(s[4] ** 2 / s[0] ** 2, rel=1e-12)   # r = rank: gap to 0

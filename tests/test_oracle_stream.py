@@ -44,3 +44,35 @@ def test_keep_rate_and_series_independence():
     assert abs(m.mean() - 0.1) < 5 * np.sqrt(0.1 * 0.9 / m.size)
     # different series see different coins at the same ticks
     assert np.mean(m[0] == m[1]) < 0.9
+
+
+def test_mask_words_ticks_against_one_block_per_word():
+    from oracle.philox import mask_words_ticks
+    seed = 0xDEADBEEF12345
+    series = np.array([0, 1, 7, 2**31 + 3], dtype=np.uint64)[:, None]
+    ticks = np.array([0, 1, 2, 3, 4, 5, 2**32 * 4 + 2, 2**40 + 7], dtype=np.uint64)[None, :]
+    got = mask_words_ticks(series, ticks, seed)
+    for a, j in enumerate(series[:, 0]):
+        for b, tau in enumerate(ticks[0]):
+            j, tau = int(j), int(tau)
+            q = tau // 4
+            w = philox_block((q & 0xFFFFFFFF, q >> 32, j, 0), (seed & 0xFFFFFFFF, seed >> 32))
+            assert int(got[a, b]) == w[tau % 4], (j, tau)
+
+
+def test_coo_and_dense_of_a_stream_window():
+    """The COO list and dense X-hat of a tick-keyed window follow its mask,
+    and two overlapping windows of one stream agree on the shared ticks."""
+    rng = np.random.default_rng(4)
+    Xl = rng.standard_normal((3, 2, 60)).astype(np.float32)
+    p, seed = 0.3, 99
+    a, b = Xl[..., 0:40], Xl[..., 25:60]                   # ticks 100..139 and 125..159
+    mask = _brute(a.shape, p, seed, 100)
+    coo = O.sample_coo_ticks(np.ascontiguousarray(a), p, seed, 100)
+    np.testing.assert_array_equal(coo.idx, np.flatnonzero(mask.ravel()))
+    np.testing.assert_array_equal(coo.val, a.ravel()[coo.idx])
+    assert coo.sumsq == float(np.sum(a.ravel()[coo.idx].astype(np.float64) ** 2))
+    Xa = O.sampled_tensor_ticks(np.ascontiguousarray(a), p, seed, 100)
+    np.testing.assert_array_equal(Xa, np.where(mask, a.astype(np.float64) / p, 0.0))
+    Xb = O.sampled_tensor_ticks(np.ascontiguousarray(b), p, seed, 125)
+    np.testing.assert_array_equal(Xa[..., 25:40], Xb[..., 0:15])
