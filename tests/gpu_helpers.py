@@ -19,16 +19,19 @@ def pack_mask(mask_flat: np.ndarray, nwords: int) -> np.ndarray:
     return np.packbits(bits, bitorder="little").view("<u8")
 
 
-def oracle_sweep_with_gaps(Xh, factors, ranks, first_mode=0):
+def oracle_sweep_with_gaps(Xh, factors, ranks, first_mode=0, sing=None):
     """One oracle HOOI sweep that also returns, per updated mode, the
-    relative eigengap and the Davis-Kahan FP32 bound of Y_(n)."""
+    relative eigengap and the Davis-Kahan FP32 bound of Y_(n); with a dict
+    `sing`, also the singular values of each Y_(n) in it."""
     A = [np.array(a, dtype=np.float64) for a in factors]
     gaps, dk = {}, {}
     for n in range(first_mode, Xh.ndim):
         Yn = O.unfold(O.ttm_chain(Xh, A, n), n)
         gaps[n] = O.eigengap(Yn, ranks[n])
         dk[n] = O.davis_kahan_bound(Yn, ranks[n], 2.0 ** -24)
-        A[n] = O.leading_left_singular_vectors(Yn, ranks[n])[0]
+        A[n], s = O.leading_left_singular_vectors(Yn, ranks[n])
+        if sing is not None:
+            sing[n] = s
     return A, gaps, dk
 
 
@@ -81,3 +84,33 @@ def load_factors(dec, factors):
     import torch
     for f, a in zip(dec.factors, factors):
         f.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)))
+
+
+def columns_elementwise(A_ref, A, s, u=2.0 ** -24, base=1e-5):
+    """Column by column, entry by entry: each column of A obeys the sign
+    rule (its entry of largest magnitude is positive, up to a tie within
+    1e-6), and where the eigenvalue lambda_i = s_i^2 of that column is
+    separated from its neighbours by g_i, the entries agree with A_ref's
+    within max(1e-5, 4 u sum(s^2) / g_i) (1e-5 alone when g_i >= 1e-3
+    lambda_1): the Davis-Kahan bound for one eigenvector.  The comparison
+    aligns the sign first, so a tie in the sign rule is not counted twice.
+    Returns the worst ratio of difference to bound (<= 1 passes)."""
+    A_ref = np.asarray(A_ref, np.float64)
+    A = np.asarray(A, np.float64)
+    lam = np.asarray(s, np.float64) ** 2
+    worst = 0.0
+    for i in range(A.shape[1]):
+        col = A[:, i]
+        mags = np.abs(col)
+        k = int(np.argmax(mags))
+        assert col[k] > 0 or np.sum(mags >= mags[k] * (1 - 1e-6)) > 1, ("sign rule", i)
+        left = lam[i - 1] - lam[i] if i > 0 else np.inf
+        right = lam[i] - lam[i + 1] if i + 1 < lam.size else lam[i]
+        g = min(left, right)
+        if g >= 1e-3 * lam[0]:
+            tol = base
+        else:
+            tol = max(base, min(2.0, 4.0 * u * float(lam.sum()) / g)) if g > 0 else 2.0
+        sg = 1.0 if float(col @ A_ref[:, i]) >= 0 else -1.0
+        worst = max(worst, float(np.abs(sg * col - A_ref[:, i]).max()) / tol)
+    return worst

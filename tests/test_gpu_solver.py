@@ -7,8 +7,8 @@ import pytest
 
 import synth
 from oracle import mach as O
-from tests.gpu_helpers import (load_factors, oracle_sweep_with_gaps, project, recon_rel_error, rel,
-                               say, sin_theta, subspace_tol)
+from tests.gpu_helpers import (columns_elementwise, load_factors, oracle_sweep_with_gaps, project,
+                               recon_rel_error, rel, say, sin_theta, subspace_tol)
 
 pytestmark = pytest.mark.gpu
 
@@ -66,8 +66,10 @@ def test_hosvd_matches_oracle(name):
         Un = O.unfold(Xh, n)
         tol = subspace_tol(O.eigengap(Un, ranks[n]), O.davis_kahan_bound(Un, ranks[n], 2.0**-24))
         np.testing.assert_allclose(A_g.T @ A_g, np.eye(ranks[n]), atol=1e-12)
-        say(f"  hosvd mode {n}: sin_theta {sin_theta(A_o, A_g):.3e} tol {tol:.1e}")
+        w = columns_elementwise(A_o, A_g, np.linalg.svd(Un, compute_uv=False))
+        say(f"  hosvd mode {n}: sin_theta {sin_theta(A_o, A_g):.3e} tol {tol:.1e}; columns {w:.2e} of bound")
         assert sin_theta(A_o, A_g) <= tol, (n, sin_theta(A_o, A_g), tol)
+        assert w <= 1.0, (n, w)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -91,13 +93,17 @@ def test_sweeps_one_step_and_end_to_end(name):
             used = M.solver_stats(dec.solver)["jacobi_sweeps"][0]
             say(f"  sweep {it} mode 0: block iteration, {used - 3000} Rayleigh-Ritz rounds")
             assert 3000 < used <= 3008, used
-        A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_ref, ranks)
+        sing = {}
+        A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_ref, ranks, sing=sing)
         for n in range(len(ranks)):
             A_g = dec.factors[n].cpu().numpy()
             np.testing.assert_allclose(A_g.T @ A_g, np.eye(ranks[n]), atol=1e-12)
             s = sin_theta(A_one[n], A_g)
-            say(f"  sweep {it} mode {n}: sin_theta {s:.3e} gap {gaps[n]:.2e} tol {subspace_tol(gaps[n], dk[n]):.1e}")
+            w = columns_elementwise(A_one[n], A_g, sing[n])
+            say(f"  sweep {it} mode {n}: sin_theta {s:.3e} gap {gaps[n]:.2e} "
+                f"tol {subspace_tol(gaps[n], dk[n]):.1e}; columns {w:.2e} of bound")
             assert s <= subspace_tol(gaps[n], dk[n]), (it, n, s, gaps[n])
+            assert w <= 1.0, (it, n, w)
         A_ref, tr = O.hooi_sweep(Xh, A_ref, ranks)
         fit_o = O.fit_from_norms(n2, tr[-1])
         assert abs(float(dec.fit.cpu()) - fit_o) < 1e-5, (float(dec.fit.cpu()), fit_o)
@@ -108,6 +114,7 @@ def test_sweeps_one_step_and_end_to_end(name):
     assert st == 0
     G_o = O.core(Xh, A_ref)
     assert rel(G, G_o) < 2e-5
+    np.testing.assert_allclose(G, G_o, rtol=0, atol=2e-5 * np.abs(G_o).max())
     assert abs(float(dec.norm2.cpu()) - float(np.sum(G_o ** 2))) < 4e-5 * float(np.sum(G * G))
     # end to end: a GPU run left to itself reaches the oracle's reconstruction error
     say("free run", name)
@@ -133,8 +140,10 @@ def test_warm_start_partial_sweep():
     assert dec.status()[0] == 0
     for n in (0, 1):
         np.testing.assert_array_equal(dec.factors[n].cpu().numpy(), A_in[n])
-    A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_in, ranks, first_mode=2)
+    sing = {}
+    A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_in, ranks, first_mode=2, sing=sing)
     assert sin_theta(A_one[2], dec.factors[2].cpu().numpy()) <= subspace_tol(gaps[2], dk[2])
+    assert columns_elementwise(A_one[2], dec.factors[2].cpu().numpy(), sing[2]) <= 1.0
 
 
 def test_exact_recovery_noiseless_p1():
@@ -191,8 +200,10 @@ def test_full_size_monitoring_window():
         Un = O.unfold(Xh, n)
         tol = subspace_tol(O.eigengap(Un, ranks[n]), O.davis_kahan_bound(Un, ranks[n], 2.0**-24))
         s = sin_theta(A_ref[n], A_h[n])
-        say(f"  hosvd mode {n}: sin_theta {s:.3e} tol {tol:.1e}")
+        w = columns_elementwise(A_ref[n], A_h[n], np.linalg.svd(Un, compute_uv=False))
+        say(f"  hosvd mode {n}: sin_theta {s:.3e} tol {tol:.1e}; columns {w:.2e} of bound")
         assert s <= tol, (n, s, tol)
+        assert w <= 1.0, (n, w)
     for _ in range(sweeps):
         A_ref, tr = O.hooi_sweep(Xh, A_ref, ranks)
     n2 = float(np.sum(Xh * Xh))
@@ -211,14 +222,19 @@ def test_full_size_monitoring_window():
     load_factors(dec, A_ref)
     dec.sweep()
     assert dec.status()[0] == 0
-    A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_ref, ranks)
+    sing = {}
+    A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_ref, ranks, sing=sing)
     for n in range(3):
         A_n = dec.factors[n].cpu().numpy()
         np.testing.assert_allclose(A_n.T @ A_n, np.eye(ranks[n]), atol=1e-12)
         s, tol = sin_theta(A_one[n], A_n), subspace_tol(gaps[n], dk[n])
-        say(f"  sweep mode {n}: sin_theta {s:.3e} gap {gaps[n]:.2e} tol {tol:.1e}")
+        w = columns_elementwise(A_one[n], A_n, sing[n])
+        say(f"  sweep mode {n}: sin_theta {s:.3e} gap {gaps[n]:.2e} tol {tol:.1e}; columns {w:.2e} of bound")
         assert s <= tol, (n, s, tol)
+        assert w <= 1.0, (n, w)
     load_factors(dec, A_one)
     G = dec.core().cpu().numpy()
     assert dec.status()[0] == 0
-    assert rel(G, O.core(Xh, A_one)) < 2e-5
+    G_o = O.core(Xh, A_one)
+    assert rel(G, G_o) < 2e-5
+    np.testing.assert_allclose(G, G_o, rtol=0, atol=2e-5 * np.abs(G_o).max())
