@@ -7,7 +7,7 @@ import pytest
 import synth
 from oracle import mach as O
 from oracle import segments as S
-from tests.gpu_helpers import pack_mask, say, sin_theta, subspace_tol
+from tests.gpu_helpers import columns_elementwise, pack_mask, say, sin_theta, subspace_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -194,7 +194,9 @@ def test_tick_keyed_window_through_hosvd():
     for n, A_o in enumerate(O.hosvd_factors(Xh, ranks)):
         Un = O.unfold(Xh, n)
         tol = subspace_tol(O.eigengap(Un, ranks[n]), O.davis_kahan_bound(Un, ranks[n], 2.0**-24))
-        assert sin_theta(A_o, dec.factors[n].cpu().numpy()) <= tol
+        A_g = dec.factors[n].cpu().numpy()
+        assert sin_theta(A_o, A_g) <= tol
+        assert columns_elementwise(A_o, A_g, np.linalg.svd(Un, compute_uv=False)) <= 1.0
 
 
 DEGENERATE = [
