@@ -12,12 +12,40 @@ the modes into head modes 0..h-1 and tail modes h..d-1:
     ordered by the head coordinates taken in a given order (outermost
     first), with column pointers.
 Both are written here as sorts and counts (numpy lexsort / bincount), which
-is their definition.  Pinned by tests/test_oracle_segments.py against
-brute-force Python loops.
+is their definition.  `head_split` states which split and head order the
+library declares for a shape (mach_layout_info), so that a test takes them
+from this stated rule and never from the library.  Pinned by
+tests/test_oracle_segments.py against brute-force Python loops, against the
+rows of Section 2.1's matricization, and (host side only) against the
+library's declared split.
 """
 from __future__ import annotations
 
 import numpy as np
+
+
+def head_split(shape):
+    """The split of the modes into head modes 0..h-1 and tail modes h..d-1
+    and the order of the head coordinates inside a tail column, by the rule
+    the library states: h ranges over [max(1, d-2), min(2, d-1)] (d//2 when
+    that range is empty), and the h whose head rows and tail columns are the
+    most balanced (smallest |log2 MH - log2 MT|, the first on ties) is taken;
+    head coordinates are ordered by ascending (dimension, mode), outermost
+    first, so the largest head mode varies fastest."""
+    dims = [int(x) for x in shape]
+    d = len(dims)
+    N = float(np.prod(dims))
+    lo, hi = max(1, d - 2), min(2, d - 1)
+    if lo > hi:
+        lo = hi = d // 2
+    best, bestv = lo, None
+    for h in range(lo, hi + 1):
+        mh = float(np.prod(dims[:h]))
+        v = abs(np.log2(mh) - np.log2(N / mh))
+        if bestv is None or v < bestv - 1e-12:
+            best, bestv = h, v
+    perm = sorted(range(best), key=lambda m: (dims[m], m))
+    return best, perm
 
 
 def row_pointers(idx: np.ndarray, shape, h: int) -> np.ndarray:

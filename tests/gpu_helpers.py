@@ -35,6 +35,28 @@ def oracle_sweep_with_gaps(Xh, factors, ranks, first_mode=0, sing=None):
     return A, gaps, dk
 
 
+def spectrum(M):
+    """Singular values of M (descending) from the eigenvalues of its
+    smaller-side Gram in float64: a fast test-side measure for very wide
+    unfoldings (the oracle's own factors always come from its SVD)."""
+    M = np.asarray(M, np.float64)
+    G = M @ M.T if M.shape[0] <= M.shape[1] else M.T @ M
+    w = np.linalg.eigvalsh(G)[::-1]
+    return np.sqrt(np.clip(w, 0.0, None))
+
+
+def gap_and_dk(s, r, u=2.0 ** -24):
+    """From singular values s: the relative eigengap (lambda_r - lambda_{r+1})
+    / lambda_1 of the Gram and the Davis-Kahan bound 4 u sum(lambda) /
+    (lambda_r - lambda_{r+1}), as the oracle's eigengap and
+    davis_kahan_bound compute them from the matrix."""
+    lam = np.concatenate([np.asarray(s, np.float64) ** 2, np.zeros(max(0, r + 1 - len(s)))])
+    gap = lam[r - 1] - lam[r]
+    rel_gap = float(gap / lam[0]) if lam[0] > 0 else 0.0
+    dk = float("inf") if gap <= 0 else float(4 * u * lam.sum() / gap)
+    return rel_gap, dk
+
+
 def subspace_tol(gap, dk, base=1e-5):
     """1e-5 where the eigengap is healthy (>= 1e-3); otherwise the stated
     Davis-Kahan bound (never below 1e-5)."""

@@ -116,3 +116,16 @@ def test_sample_ticks_rejects_wrapping_ticks(M):
     assert rc == M.MACH_EINVAL
     rc = M.LIB.mach_sample_ticks(C.byref(s), M.MACH_F32, fake, 0.5, 1, 0, fake, nb - 1, cap, None)
     assert rc == M.MACH_ENOMEM
+
+
+def test_layout_split_follows_the_stated_rule(M):
+    """mach_layout_info agrees with the rule stated in the segment oracle
+    (which the GPU layout tests use instead of asking the library)."""
+    from oracle import segments as S
+    shapes = [(128, 16, 16384), (64, 32, 48), (16, 16, 16, 64), (300, 200), (37, 53), (5, 7, 9),
+              (3, 5, 7, 11), (64, 64, 64, 256), (96, 12, 12), (600, 12, 12), (16, 16, 16, 256),
+              (1024, 1024, 2047), (7, 5, 333), (4, 4, 4, 97), (2, 3, 4, 5, 6), (3, 3, 3, 3, 3, 3),
+              (9, 2), (2, 9), (8, 8, 8, 8), (1, 5, 7), (96, 80, 6), (6, 5, 7)]
+    for shape in shapes:
+        assert M.layout_info(shape) == S.head_split(shape), shape
+

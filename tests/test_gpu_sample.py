@@ -51,7 +51,7 @@ def test_sample_and_layouts_bit_exact(name, shape, dt, p, seed, win):
     pc = np.array([bin(int(w)).count("1") for w in words], dtype=np.int64)
     wr = sw.u32("wrank", nwords + 1).astype(np.int64)
     np.testing.assert_array_equal(wr, np.concatenate([[0], np.cumsum(pc)]))
-    h, perm = M.layout_info(shape)
+    h, perm = S.head_split(shape)
     MH = int(np.prod(shape[:h]))
     MT = N // MH
     np.testing.assert_array_equal(sw.u32("rowptr", MH + 1), S.row_pointers(coo.idx, shape, h))
@@ -84,40 +84,43 @@ def test_invalid_arguments_rejected_on_host():
         M.sample(X, 0.5, 0, 0, cap=0)
 
 
-def test_full_size_monitoring_tensor_sampled_positions():
-    """128x16x16384 at p = 0.1 (the benchmarked workload): the kept count is
-    Binomial, and the mask, the kept entries and the column copy agree with
-    the oracle on sampled windows of the linear index."""
+FULL = [("monitoring-128x16x16384-p0.1", 0.1, 20262), ("monitoring-128x16x16384-p0.01", 0.01, 20262),
+        ("voxel-64x64x64x256-p0.05", 0.05, 20263)]
+
+
+@pytest.mark.parametrize("name,p,seed", FULL, ids=[c[0] for c in FULL])
+def test_full_size_whole_mask(name, p, seed):
+    """The full-size workloads (the monitoring window at p = 0.1 and 0.01,
+    the 4-way voxel tensor at p = 0.05): the whole keep bitmap (every coin),
+    the kept entries, their sum of squares and both layouts agree with the
+    oracle bit for bit."""
     import torch
     from paper_0909_4969_amd import mach as M
-    shape, p, seed, win = (128, 16, 16384), 0.1, 20262, 0
-    X, _ = synth.workload2(shape)
-    say("sample full-size", shape)
+    win = 0
+    X, _ = synth.workload3() if name.startswith("voxel") else synth.workload2()
+    shape = X.shape
+    say("sample full-size", name, shape)
     sw = M.sample(torch.from_numpy(X).cuda(), p, seed, win)
     st, nnz, ss = sw.status()
     assert st == 0
     N = X.size
-    q = O.keep_threshold(p) / 2**32
-    assert abs(nnz - N * q) < 6 * math.sqrt(N * q * (1 - q))
+    coo = O.sample_coo(X, p, seed, win)
+    assert nnz == coo.nnz
+    nwords = ((N + 16383) // 16384) * 256
+    words = sw.u64("bitmap", nwords)
+    np.testing.assert_array_equal(words, pack_mask(O.sample_mask(shape, p, seed, win).ravel(), nwords))
     idx, val = sw.entries("coo_l", nnz)
-    assert np.all(np.diff(idx.astype(np.int64)) > 0)
-    rng = np.random.default_rng(1)
-    flat = X.ravel()
-    for start in rng.integers(0, N - 70000, 8):
-        lo, hi = int(start), int(start) + 65536
-        lin = np.arange(lo, hi, dtype=np.uint64)
-        keep = O.mask_words(lin, seed, win).astype(np.uint64) < np.uint64(O.keep_threshold(p))
-        want = np.flatnonzero(keep).astype(np.int64) + lo
-        sel = (idx >= lo) & (idx < hi)
-        np.testing.assert_array_equal(idx[sel].astype(np.int64), want)
-        np.testing.assert_array_equal(val[sel], flat[want])
-    assert abs(ss - float(np.sum(flat[idx].astype(np.float64) ** 2))) <= 1e-10 * ss
-    h, perm = M.layout_info(shape)
-    order, colptr = S.column_order(idx, shape, h, perm)
-    MT = N // int(np.prod(shape[:h]))
-    np.testing.assert_array_equal(sw.u32("colptr", MT + 1), colptr)
-    tidx, _ = sw.entries("coo_t", nnz)
-    np.testing.assert_array_equal(tidx, idx[order])
+    np.testing.assert_array_equal(idx, coo.idx)
+    np.testing.assert_array_equal(val.view(np.uint32), coo.val.view(np.uint32))
+    assert abs(ss - coo.sumsq) <= 1e-12 * coo.sumsq
+    h, perm = S.head_split(shape)
+    MH = int(np.prod(shape[:h]))
+    np.testing.assert_array_equal(sw.u32("rowptr", MH + 1), S.row_pointers(coo.idx, shape, h))
+    order, colptr = S.column_order(coo.idx, shape, h, perm)
+    np.testing.assert_array_equal(sw.u32("colptr", N // MH + 1), colptr)
+    tidx, tval = sw.entries("coo_t", nnz)
+    np.testing.assert_array_equal(tidx, coo.idx[order])
+    np.testing.assert_array_equal(tval.view(np.uint32), coo.val[order].view(np.uint32))
 
 
 TICK_CASES = [
@@ -149,7 +152,7 @@ def test_tick_keyed_sample_bit_exact(name, shape, dt, p, seed, tick0):
     nwords = ((N + 16383) // 16384) * 256
     words = sw.u64("bitmap", nwords)
     np.testing.assert_array_equal(words, pack_mask(O.sample_mask_ticks(shape, p, seed, tick0).ravel(), nwords))
-    h, perm = M.layout_info(shape)
+    h, perm = S.head_split(shape)
     MH = int(np.prod(shape[:h]))
     np.testing.assert_array_equal(sw.u32("rowptr", MH + 1), S.row_pointers(coo.idx, shape, h))
 
@@ -234,7 +237,7 @@ def test_degenerate_sample_sets_status_and_solver_does_nothing(name, p, seed, ki
     coo = O.sample_coo(X, p, seed, 0)
     idx, _ = dec.sw.entries("coo_l", nnz)
     np.testing.assert_array_equal(idx, coo.idx)
-    h, _ = M.layout_info(shape)
+    h, _ = S.head_split(shape)
     MH = int(np.prod(shape[:h]))
     np.testing.assert_array_equal(dec.sw.u32("rowptr", MH + 1), S.row_pointers(coo.idx, shape, h))
     say("solver on degenerate sample", name)
@@ -280,7 +283,7 @@ def test_maximum_size_sample_sampled_positions():
         want = np.flatnonzero(keep).astype(np.int64) + lo
         sel = (idx >= lo) & (idx < hi)
         np.testing.assert_array_equal(idx[sel].astype(np.int64), want)
-    h, perm = M.layout_info(shape)
+    h, perm = S.head_split(shape)
     MH = int(np.prod(shape[:h]))
     order, colptr = S.column_order(idx, shape, h, perm)
     np.testing.assert_array_equal(sw.u32("colptr", N // MH + 1), colptr)

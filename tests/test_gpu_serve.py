@@ -3,13 +3,15 @@ mix of concurrent windows (bit for bit: every window has its own
 workspaces and the kernels are deterministic); warm-started windows follow
 the oracle's own chain (a stream's first window: HOSVD + sweeps; later
 windows: time-mode update from the previous host/metric factors, then
-sweeps); the HBM budget limits what is in flight."""
+sweeps) within 1e-5 in subspace angle where the eigengap at the oracle's
+result is at least 1e-3 of the largest eigenvalue, else within the
+Davis-Kahan bound; the HBM budget limits what is in flight."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import mach as O
-from tests.gpu_helpers import project, say, sin_theta
+from tests.gpu_helpers import oracle_sweep_with_gaps, project, say, sin_theta, subspace_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -90,13 +92,14 @@ def test_warm_chain_matches_oracle():
         prev[r.stream_id] = A
         fit_o = O.fit_from_norms(n2, tr[-1])
         A_g = [f.cpu().numpy() for f in g.factors]
+        _, gaps, dk = oracle_sweep_with_gaps(Xh, A, RANKS)
         for n in range(3):
-            s = sin_theta(A[n], A_g[n])
-            say(f"  window {r.req_id} mode {n}: sin_theta {s:.2e}")
-            assert s <= 1e-4, (r.req_id, n, s)
+            s, tol = sin_theta(A[n], A_g[n]), subspace_tol(gaps[n], dk[n])
+            say(f"  window {r.req_id} mode {n}: sin_theta {s:.2e} gap {gaps[n]:.2e} tol {tol:.1e}")
+            assert s <= tol, (r.req_id, n, s, tol)
         assert abs(g.fit - fit_o) < 1e-5, (g.fit, fit_o)
         G_p = project(Xh, A_g)      # the core of the returned factors, formed on the host
-        np.testing.assert_allclose(g.core.cpu().numpy(), G_p, rtol=0, atol=2e-5 * np.abs(G_p).max())
+        np.testing.assert_allclose(g.core.cpu().numpy(), G_p, rtol=0, atol=1e-5 * np.abs(G_p).max())
 
 
 def test_hbm_budget_limits_inflight():
@@ -153,8 +156,9 @@ def test_sliding_windows_with_stream_coins_match_oracle():
         g = res[w]
         assert g.warm == (w > 0)
         assert g.nnz == int(np.count_nonzero(Xh))
+        _, gaps, dk = oracle_sweep_with_gaps(Xh, A, RANKS)
         for n in range(3):
-            s = sin_theta(A[n], g.factors[n].cpu().numpy())
-            say(f"  window {w} mode {n}: sin_theta {s:.2e}")
-            assert s <= 1e-4, (w, n, s)
+            s, tol = sin_theta(A[n], g.factors[n].cpu().numpy()), subspace_tol(gaps[n], dk[n])
+            say(f"  window {w} mode {n}: sin_theta {s:.2e} gap {gaps[n]:.2e} tol {tol:.1e}")
+            assert s <= tol, (w, n, s, tol)
         assert abs(g.fit - O.fit_from_norms(float(np.sum(Xh * Xh)), tr[-1])) < 1e-5

@@ -7,8 +7,8 @@ import pytest
 
 import synth
 from oracle import mach as O
-from tests.gpu_helpers import (columns_elementwise, load_factors, oracle_sweep_with_gaps, project,
-                               recon_rel_error, rel, say, sin_theta, subspace_tol)
+from tests.gpu_helpers import (columns_elementwise, gap_and_dk, load_factors, oracle_sweep_with_gaps,
+                               project, recon_rel_error, rel, say, sin_theta, spectrum, subspace_tol)
 
 pytestmark = pytest.mark.gpu
 
@@ -35,11 +35,34 @@ def _big_side():
     X, _ = synth.workload1(shape=(96, 80, 6), ranks=(5, 5, 3), seed=9)
     return X.astype(np.float32), (5, 5, 3), 0.3, 12
 
+def _row96():
+    X, _ = synth.workload1(shape=(96, 12, 12), ranks=(8, 10, 10), seed=13)
+    return X.astype(np.float32), (8, 10, 10), 0.3, 14
+def _col216():
+    X, _ = synth.workload3(shape=(16, 16, 16, 256), ranks=(6, 6, 6, 6), seed=15)
+    return X, (6, 6, 6, 6), 0.2, 16
+def _col100():
+    X, _ = synth.workload1(shape=(600, 12, 12), ranks=(10, 10, 10), seed=17)
+    return X.astype(np.float32), (10, 10, 10), 0.3, 18
+
 # monitor-128x16x2048: mode 0 has I = 128 > K = 64 with R = 8, the column-side
-# block subspace iteration on Y Y^T
+# block subspace iteration on Y Y^T.  Sweep Grams with a side above 64 (the
+# block subspace iteration of the sweep): rowside96 (mode 0, I = 96 < K =
+# 100, row side), colside216 (mode 3, K = 216 < I = 256, column side with
+# back-projection), colside100 (mode 0, K = 100 < I = 600).
 CASES = {"tucker-64x32x48-f64": _w1, "monitor-32x16x2048": _w2, "monitor-128x16x2048": _w2s,
          "monitor-p0.01-64x16x4096": _w2p01,
-         "voxel-16x16x16x64": _w3, "matrix-300x200": _mat, "sides>64-96x80x6": _big_side}
+         "voxel-16x16x16x64": _w3, "matrix-300x200": _mat, "sides>64-96x80x6": _big_side,
+         "rowside96-96x12x12": _row96, "colside216-16x16x16x256": _col216,
+         "colside100-600x12x12": _col100}
+
+# Core and error bars.  The float32 bar is 1e-5 relative (norm-wise) on the
+# core, so 2e-5 relative on its squared norm (d||G||^2 / ||G||^2 = 2 d||G|| /
+# ||G||), and 1e-5 of the largest entry element by element.
+CORE_REL, CORE_NORM2_REL = 1e-5, 2e-5
+# A free-running device run and the oracle's own run (three sweeps after
+# HOSVD) end at the same relative reconstruction error within 1e-5 relative.
+FREE_E_REL = 1e-5
 
 
 def _setup(name):
@@ -113,9 +136,10 @@ def test_sweeps_one_step_and_end_to_end(name):
     st, _, _ = dec.status()
     assert st == 0
     G_o = O.core(Xh, A_ref)
-    assert rel(G, G_o) < 2e-5
-    np.testing.assert_allclose(G, G_o, rtol=0, atol=2e-5 * np.abs(G_o).max())
-    assert abs(float(dec.norm2.cpu()) - float(np.sum(G_o ** 2))) < 4e-5 * float(np.sum(G * G))
+    say(f"  core rel {rel(G, G_o):.2e} max abs {np.abs(G - G_o).max() / np.abs(G_o).max():.2e} of max")
+    assert rel(G, G_o) < CORE_REL
+    np.testing.assert_allclose(G, G_o, rtol=0, atol=CORE_REL * np.abs(G_o).max())
+    assert abs(float(dec.norm2.cpu()) - float(np.sum(G_o ** 2))) < CORE_NORM2_REL * float(np.sum(G_o ** 2))
     # end to end: a GPU run left to itself reaches the oracle's reconstruction error
     say("free run", name)
     dec.hosvd()
@@ -125,8 +149,8 @@ def test_sweeps_one_step_and_end_to_end(name):
     A_g = [a.cpu().numpy() for a in dec.factors]
     e_o = O.rel_error(X, G_o, A_ref)
     e_g = recon_rel_error(X, project(Xh, A_g), A_g)
-    say(f"  rel error gpu {e_g:.8f} oracle {e_o:.8f}")
-    assert abs(e_g - e_o) <= 1e-4 * e_o + 1e-6, (e_g, e_o)
+    say(f"  rel error gpu {e_g:.8f} oracle {e_o:.8f} (difference {abs(e_g - e_o) / e_o:.2e} relative)")
+    assert abs(e_g - e_o) <= FREE_E_REL * e_o, (e_g, e_o)
 
 
 def test_warm_start_partial_sweep():
@@ -166,24 +190,38 @@ def test_exact_recovery_noiseless_p1():
     assert recon_rel_error(X, G, [a.cpu().numpy() for a in dec.factors]) < 1e-5
 
 
-def test_full_size_monitoring_window():
-    """The benchmarked window at full size, in the benchmark's launch
-    sequence: 128 x 16 x 16384 float32, p = 0.1, rank (8, 4, 16), coin toss
-    (seed 20262, window 0), HOSVD, 20 sweeps, core.  Against the oracle:
-    the HOSVD subspaces; one sweep and the core from the oracle's final
-    factors; the free-running fit and reconstruction error after 20 sweeps."""
+FULL = [("monitoring-128x16x16384-p0.1", 0.1, 20262, 20), ("monitoring-128x16x16384-p0.01", 0.01, 20262, 20),
+        ("voxel-64x64x64x256-p0.05", 0.05, 20263, 10)]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,p,seed,sweeps", FULL, ids=[c[0] for c in FULL])
+def test_full_size_window(name, p, seed, sweeps):
+    """The full-size workloads in the benchmark's launch sequence: the
+    monitoring window 128 x 16 x 16384 float32 at rank (8, 4, 16) and p in
+    {0.1, 0.01} with 20 sweeps, and the 4-way voxel tensor 64 x 64 x 64 x
+    256 float32 at rank 10^4, p = 0.05, with 10 sweeps (its last mode's
+    sweep Gram has side 256); coin toss (window 0), HOSVD, sweeps, core.
+    Against the oracle: the HOSVD subspaces; the free-running fit and
+    reconstruction error after all sweeps; one sweep and the core from the
+    oracle's final factors."""
     import torch
     from paper_0909_4969_amd import mach as M
-    shape, ranks, p, seed, sweeps = (128, 16, 16384), (8, 4, 16), 0.1, 20262, 20
-    X, _ = synth.workload2(shape)
+    if name.startswith("voxel"):
+        X, _ = synth.workload3()
+        ranks = (10, 10, 10, 10)
+    else:
+        X, _ = synth.workload2()
+        ranks = (8, 4, 16)
+    shape, d = X.shape, X.ndim
     dec = M.Decomposition(shape, ranks, p)
-    say("full size: sample + hosvd", shape)
+    say("full size: sample + hosvd", name)
     dec.sample(torch.from_numpy(X).cuda(), seed, 0)
     dec.hosvd()
     st, nnz, _ = dec.status()
     assert st == 0, st
     A_h = [a.cpu().numpy() for a in dec.factors]
-    say("full size: sweeps + core")
+    say("full size: sweeps + core", name)
     for _ in range(sweeps):
         dec.sweep()
     dec.core()
@@ -193,38 +231,43 @@ def test_full_size_monitoring_window():
     G_g = dec.G.cpu().numpy()
     fit_g = float(dec.fit.cpu())
 
+    say("oracle: coin toss", name)
     Xh = O.sampled_tensor(X, p, seed, 0)
     assert nnz == int(np.count_nonzero(Xh))
+    say("oracle: hosvd", name)
     A_ref = O.hosvd_factors(Xh, ranks)
-    for n in range(3):
-        Un = O.unfold(Xh, n)
-        tol = subspace_tol(O.eigengap(Un, ranks[n]), O.davis_kahan_bound(Un, ranks[n], 2.0**-24))
+    for n in range(d):
+        sv = spectrum(O.unfold(Xh, n))
+        tol = subspace_tol(*gap_and_dk(sv, ranks[n]))
         s = sin_theta(A_ref[n], A_h[n])
-        w = columns_elementwise(A_ref[n], A_h[n], np.linalg.svd(Un, compute_uv=False))
+        w = columns_elementwise(A_ref[n], A_h[n], sv)
         say(f"  hosvd mode {n}: sin_theta {s:.3e} tol {tol:.1e}; columns {w:.2e} of bound")
         assert s <= tol, (n, s, tol)
         assert w <= 1.0, (n, w)
+    say("oracle: sweeps", name)
     for _ in range(sweeps):
         A_ref, tr = O.hooi_sweep(Xh, A_ref, ranks)
     n2 = float(np.sum(Xh * Xh))
     fit_o = O.fit_from_norms(n2, tr[-1])
     e_o = O.rel_error(X, O.core(Xh, A_ref), A_ref)
     e_g = recon_rel_error(X, G_g, A_g)
-    for n in range(3):
+    for n in range(d):
         say(f"  after {sweeps} sweeps mode {n}: sin_theta to the oracle's {sin_theta(A_ref[n], A_g[n]):.2e}")
-    say(f"  fit gpu {fit_g:.8f} oracle {fit_o:.8f}; rel error gpu {e_g:.8f} oracle {e_o:.8f}")
+    say(f"  fit gpu {fit_g:.8f} oracle {fit_o:.8f}; rel error gpu {e_g:.8f} oracle {e_o:.8f} "
+        f"(difference {abs(e_g - e_o) / e_o:.2e} relative)")
     assert abs(fit_g - fit_o) < 1e-5, (fit_g, fit_o)
-    assert abs(e_g - e_o) <= 1e-4 * e_o + 1e-6, (e_g, e_o)
+    assert abs(e_g - e_o) <= FREE_E_REL * e_o, (e_g, e_o)
     G_p = project(Xh, A_g)
-    assert rel(G_g, G_p) < 2e-5
+    say(f"  core of the device factors: rel {rel(G_g, G_p):.2e}")
+    assert rel(G_g, G_p) < CORE_REL
 
-    say("full size: one sweep and the core from the oracle's factors")
+    say("full size: one sweep and the core from the oracle's factors", name)
     load_factors(dec, A_ref)
     dec.sweep()
     assert dec.status()[0] == 0
     sing = {}
     A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_ref, ranks, sing=sing)
-    for n in range(3):
+    for n in range(d):
         A_n = dec.factors[n].cpu().numpy()
         np.testing.assert_allclose(A_n.T @ A_n, np.eye(ranks[n]), atol=1e-12)
         s, tol = sin_theta(A_one[n], A_n), subspace_tol(gaps[n], dk[n])
@@ -236,5 +279,6 @@ def test_full_size_monitoring_window():
     G = dec.core().cpu().numpy()
     assert dec.status()[0] == 0
     G_o = O.core(Xh, A_one)
-    assert rel(G, G_o) < 2e-5
-    np.testing.assert_allclose(G, G_o, rtol=0, atol=2e-5 * np.abs(G_o).max())
+    say(f"  core rel {rel(G, G_o):.2e}")
+    assert rel(G, G_o) < CORE_REL
+    np.testing.assert_allclose(G, G_o, rtol=0, atol=CORE_REL * np.abs(G_o).max())
