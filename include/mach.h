@@ -170,6 +170,29 @@ mach_status mach_core(const void* ws_sample, uint64_t nnz_cap, const mach_shape*
                       const int32_t* ranks, double* const* A_dev, double* G_dev,
                       double* core_norm2_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* mach_core without a solver workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * mach_core minus the workspace; the core's scratch (status word, float32
+ * factor copies, the partial product over the tail modes, the last mode's
+ * Y) lives in a fixed 16 MiB device array of the library, one per GPU, held
+ * until the process ends.  The scratch needed is
+ *   256 + sum_k 64 I_k + 4 MT KH  (+ 4 I_d K_d when the last mode is one of
+ *   two tail modes)
+ * bytes, each term rounded up to 256, with MT the product of the tail
+ * dimensions and KH the product of the head ranks (mach_layout_info gives
+ * the split); above 16 MiB the call returns MACH_ENOMEM and enqueues
+ * nothing.  The call allocates nothing (no hipMalloc or hipFree, no
+ * allocating library routine) and clears what must start at zero with a
+ * kernel, not a memset.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (different streams, or threads) race and
+ * must be serialised by the caller.  The first call on a device looks up
+ * the array's device address (hipGetSymbolAddress) and may return
+ * MACH_EDEVICE if that fails. */
+mach_status mach_core_noalloc(const void* ws_sample, uint64_t nnz_cap, const mach_shape* s,
+                              const int32_t* ranks, double* const* A_dev, double* G_dev,
+                              double* core_norm2_dev, void* stream);
+
 /* Clears the solver workspace's status word and eigen warm-start state.
  * A fresh solver workspace must be reset (mach_hosvd does it) before
  * mach_hooi_sweep or mach_core use it. */

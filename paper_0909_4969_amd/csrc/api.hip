@@ -592,6 +592,103 @@ mach_status mach_core(const void* ws_sample, uint64_t nnz_cap, const mach_shape*
   return ok ? MACH_OK : MACH_EDEVICE;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free core: the scratch of mach_core (status word, float32
+// factor copies, the tail-side partial product and the last mode's Y) in a
+// fixed device array instead of a caller workspace.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kCoreScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kCoreScratchBytes];
+
+// Device address of `scratch` per device, looked up once per device with
+// that device current.  Host code never uses the array's name as an address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_ptr() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// The part of the solver layout that the core's launches touch, packed from
+// offset 0: status word and tags, float32 factor copies, TT, and Y of the
+// last mode when it is contracted from TT.  Every other offset is 0 and no
+// launch of the core reads it.
+bool make_core_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout* out) {
+  SolverLayout full;
+  if (!make_solver_layout(si, ranks, &full)) return false;
+  SolverLayout S;
+  std::memset(&S, 0, sizeof(S));
+  S.KT = full.KT;
+  S.KH = full.KH;
+  for (int k = 0; k < si.d; ++k) {
+    S.mp[k] = full.mp[k];
+    S.mp[k].ybuf = S.mp[k].V = S.mp[k].lam = S.mp[k].Q64 = 0;
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  S.status = take(256);
+  S.tags = S.status + 16;
+  for (int k = 0; k < si.d; ++k) S.af[k] = take((size_t)si.dims[k] * 16 * 4);
+  S.TT = take((size_t)si.MT * S.KH * 4);
+  ModePlan& m = S.mp[si.d - 1];
+  m.ybuf = m.contract_mode >= 0 ? take((size_t)m.I * m.K * 4) : S.TT;
+  S.total = o;
+  *out = S;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+mach_status mach_core_noalloc(const void* ws_sample, uint64_t nnz_cap, const mach_shape* s,
+                              const int32_t* ranks, double* const* A_dev, double* G_dev,
+                              double* core_norm2_dev, void* stream) {
+  if (!ws_sample || !A_dev || !ranks || !G_dev) return MACH_EINVAL;
+  ShapeInfo si;
+  if (!make_shape_info(s, &si)) return MACH_EINVAL;
+  if (si.d > 4) return MACH_EUNSUPPORTED;
+  if (nnz_cap < 1 || nnz_cap > (1ull << 31)) return MACH_EINVAL;
+  if ((uintptr_t)ws_sample & 255) return MACH_EINVAL;
+  for (int k = 0; k < si.d; ++k)
+    if (!A_dev[k]) return MACH_EINVAL;
+  SolverLayout SL;
+  if (!make_core_layout(si, ranks, &SL)) return MACH_EINVAL;
+  if (SL.total > kCoreScratchBytes) return MACH_ENOMEM;
+  char* w = (char*)scratch_ptr();
+  if (!w) return MACH_EDEVICE;
+  const SampleLayout L = sample_layout(si, nnz_cap);
+  const SparsePtrs sp = sparse_ptrs((const char*)ws_sample, L);
+  hipStream_t st = (hipStream_t)stream;
+  const double density = (double)nnz_cap / (double)si.N;
+  // The status word left by the previous call is cleared by a fill kernel
+  // (the sequence stays capturable: no memset node).
+  bool ok = launch_solver_init(SL, w, st) == hipSuccess;
+  ok = ok && launch_factors_to_f32(si, SL, w, A_dev, ranks, sp.hdr, st) == hipSuccess;
+  ok = ok && launch_contract_head(si, sp, SL, w, ranks, density, 0, st) == hipSuccess;
+  ok = ok && launch_form_y(si, SL, w, si.d - 1, sp.hdr, st) == hipSuccess;
+  ok = ok && launch_core(si, SL, w, A_dev[si.d - 1], G_dev, core_norm2_dev, sp.hdr, st) ==
+                 hipSuccess;
+  return ok ? MACH_OK : MACH_EDEVICE;
+}
+
 mach_status mach_timing_enable(int32_t every) {
   if (every < 0) return MACH_EINVAL;
   g_timing.every = every;

@@ -26,7 +26,7 @@ EXPORTED = (
     "mach_solver_workspace_bytes", "mach_hosvd", "mach_hooi_sweep", "mach_core",
     "mach_solver_reset", "mach_layout_info", "mach_sample_offsets",
     "mach_read_status", "mach_status_string", "mach_host_selftest",
-    "mach_timing_enable", "mach_timing_read",
+    "mach_timing_enable", "mach_timing_read", "mach_core_noalloc",
 )
 
 
@@ -65,6 +65,7 @@ def _load():
         "mach_hosvd": (I32, [P, U64, SP, IP, P, P, SZ, P]),
         "mach_hooi_sweep": (I32, [P, U64, SP, IP, P, I32, I32, P, SZ, P, P]),
         "mach_core": (I32, [P, U64, SP, IP, P, P, P, P, SZ, P]),
+        "mach_core_noalloc": (I32, [P, U64, SP, IP, P, P, P, P]),
         "mach_solver_reset": (I32, [SP, IP, P, SZ, P]),
         "mach_layout_info": (I32, [SP, IP, IP]),
         "mach_sample_offsets": (I32, [SP, U64, ctypes.POINTER(U64), I32]),
@@ -286,6 +287,18 @@ def core(sw: SampleWorkspace, ranks, factors, solver: torch.Tensor, G=None, norm
     _check("mach_core", LIB.mach_core(sw.ptr, sw.cap, ctypes.byref(s), _ranks(ranks), _ptr_array(factors),
                                       ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(norm2.data_ptr()),
                                       ctypes.c_void_p(solver.data_ptr()), solver.numel(), _stream(stream)))
+    return G, norm2
+
+
+def core_noalloc(sw: SampleWorkspace, ranks, factors, G: torch.Tensor, norm2: torch.Tensor, stream=None):
+    """mach_core_noalloc: the core into the caller's G and norm2, with the
+    library's fixed device scratch instead of a solver workspace (nothing is
+    allocated by the call)."""
+    _factors_ok(factors, sw.shape, ranks)
+    s = Shape.of(sw.shape)
+    _check("mach_core_noalloc", LIB.mach_core_noalloc(sw.ptr, sw.cap, ctypes.byref(s), _ranks(ranks),
+                                                      _ptr_array(factors), ctypes.c_void_p(G.data_ptr()),
+                                                      ctypes.c_void_p(norm2.data_ptr()), _stream(stream)))
     return G, norm2
 
 
