@@ -3,30 +3,36 @@
 
 One step is the whole hot path over one synthetic window already resident
 in HBM: the coin toss (with the sparse layouts), HOSVD initialisation,
-`--sweeps` HOOI sweeps and the core.  The workload is the monitoring-shaped
-hosts x metrics x minutes tensor 128 x 16 x 16384 (float32, Tucker rank
-(8,4,16) + diurnal sinusoids + Pareto spikes) at p = 0.1, rank (8,4,16),
-20 sweeps.
+`--sweeps` HOOI sweeps and the core.  The headline workload is the
+monitoring-shaped hosts x metrics x minutes tensor 128 x 16 x 16384
+(float32, Tucker rank (8,4,16) + diurnal sinusoids + Pareto spikes) at
+p = 0.1, rank (8,4,16), 20 sweeps; the `voxel` block runs the 4-way
+64 x 64 x 64 x 256 workload (p = 0.05, rank 10^4, 10 sweeps) the same way.
 
 value = kept entries x sweeps / step time (sampled nnz per second of HOOI
 sweeping, with sampling, HOSVD and core time included in the step).
 
-roofline: the sparse tensor-times-matrix pass that takes the most time,
-timed per dispatch with HIP events over the timed steps; its algorithmic
-bytes per launch are 8 bytes per kept entry (uint32 index + float32 value)
-plus its float32 output and its segment pointers.
+roofline: the slower sparse tensor-times-matrix pass, timed per launch with
+HIP events on its stream, cold (1 GiB written before each timed sweep, so
+the kept entries come from HBM); warm figures beside.  Algorithmic bytes
+per launch: 8 per kept entry (uint32 index + float32 value) plus the
+float32 output and the segment pointers.
 
-cpu_baseline: the FP64 numpy oracle on the same tensor (coin toss, HOSVD
-and core timed in full; two sweeps timed and the rest extrapolated).
+cpu_baseline: the FP64 numpy oracle on the benchmarked window, whole job
+timed; accuracy: the device result of that window against the oracle's
+(principal-angle sines, reconstruction errors e and e', core, fit).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -46,7 +52,8 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--seed", type=int, default=20262)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--no-voxel", action="store_true",
+                    help="skip the 64x64x64x256 voxel workload block")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="windows of the serving run (0: skip it)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -80,9 +87,14 @@ def pmc_summary(fetch_dir, write_dir, copy_mib):
         for r in rows:
             n = r["Kernel_Name"]
             m = re.search(r"k_spc<(\d), (\d+), (\d+), (\d), (\d)(?:, \d)?>", n)
+            mt = re.search(r"k_rows_tiled<(\d+), (\d)>", n)
             key = None
             if m and m.group(5) == "0":      # float32 factors (the timed path)
                 key = "ttm_tail_cols" if m.group(4) == "1" else "ttm_head_rows"
+            elif mt and mt.group(2) == "0":
+                key = "ttm_head_rows_tiles"
+            elif "k_rows_tiled_sum" in n:
+                key = "ttm_head_rows_sum"
             elif "copyBuffer" in n and int(r["Grid_Size"]) == big:
                 key = "copy"
             if key:
@@ -90,6 +102,10 @@ def pmc_summary(fetch_dir, write_dir, copy_mib):
         return {k: sum(v) / len(v) for k, v in acc.items()}
 
     fetch, write = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+    # the tiled head-row pass is two launches: tiles, then the partial sums
+    for d in (fetch, write):
+        if "ttm_head_rows_tiles" in d:
+            d["ttm_head_rows"] = d.pop("ttm_head_rows_tiles") + d.pop("ttm_head_rows_sum", 0.0)
     # the counter runs' output folders, relative to the repository root ($R)
     fd, wd = os.path.relpath(fetch_dir, ROOT), os.path.relpath(write_dir, ROOT)
     true_bytes = copy_mib * (1 << 20)
@@ -131,8 +147,10 @@ def traffic_from_profiles(which):
     return d.get("bytes_per_launch", {}).get(which)
 
 
-def cpu_baseline(X, p, seed, ranks, sweeps, cpu_sweeps, nnz):
-    import numpy as np
+def cpu_baseline(X, p, seed, ranks, sweeps, nnz, gpu_factors, gpu_core, gpu_fit):
+    """The FP64 numpy oracle on the benchmarked window (window 0): coin toss,
+    HOSVD, all sweeps and the core, timed in full on the host cores; then
+    the device result of the same window measured against it."""
     from threadpoolctl import threadpool_info
 
     from oracle import mach as O
@@ -142,24 +160,39 @@ def cpu_baseline(X, p, seed, ranks, sweeps, cpu_sweeps, nnz):
     t1 = time.perf_counter()
     A = O.hosvd_factors(Xh, ranks)
     t2 = time.perf_counter()
-    for _ in range(cpu_sweeps):
-        A, _ = O.hooi_sweep(Xh, A, ranks)
+    fits = []
+    n2 = float(np.sum(Xh * Xh))
+    for _ in range(sweeps):
+        A, tr = O.hooi_sweep(Xh, A, ranks)
+        fits.append(O.fit_from_norms(n2, tr[-1]))
     t3 = time.perf_counter()
-    O.core(Xh, A)
+    G = O.core(Xh, A)
     t4 = time.perf_counter()
-    per_sweep = (t3 - t2) / cpu_sweeps
-    t_job = (t1 - t0) + (t2 - t1) + sweeps * per_sweep + (t4 - t3)
-    del np
-    return {
+    t_job = t4 - t0
+    del Xh
+    cb = {
         "value": nnz * sweeps / t_job,
         "unit": "nnz/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"FP64 numpy oracle on the same {X.shape[0]}x{X.shape[1]}x{X.shape[2]} window: coin "
-                   f"toss {t1 - t0:.1f}s, HOSVD {t2 - t1:.1f}s and core {t4 - t3:.2f}s timed in full, "
-                   f"{cpu_sweeps} of {sweeps} sweeps timed ({per_sweep:.3f}s each) and the rest "
-                   f"extrapolated; job {t_job:.1f}s"),
+        "cpu": cpu_model(),
+        "sample": (f"FP64 numpy oracle on the benchmarked {'x'.join(map(str, X.shape))} window, whole job "
+                   f"timed: coin toss {t1 - t0:.1f}s, HOSVD {t2 - t1:.1f}s, {sweeps} sweeps "
+                   f"{t3 - t2:.1f}s, core {t4 - t3:.2f}s; job {t_job:.1f}s"),
     }
+    e_o, e2_o = host_measures(X, G, A)
+    e_g, e2_g = host_measures(X, gpu_core, gpu_factors)
+    acc = {
+        "window": 0, "reference": "FP64 oracle, same coins, HOSVD + same sweeps + core",
+        "sin_theta_per_mode": [round(sin_theta_host(a, b), 9) for a, b in zip(A, gpu_factors)],
+        "rel_error_e": {"gpu": e_g, "oracle": e_o, "rel_diff": abs(e_g - e_o) / e_o},
+        "rel_error_e_prime": {"gpu": e2_g, "oracle": e2_o, "rel_diff": abs(e2_g - e2_o) / e2_o},
+        "core_rel_diff": float(np.linalg.norm(gpu_core - G) / np.linalg.norm(G)),
+        "fit": {"gpu": gpu_fit, "oracle": fits[-1]},
+        "note": "e = ||X - G x_n A_n|| / ||X|| (1 - the paper's accuracy); e' = ||X - X x_n A_n A_n^T|| "
+                "/ ||X||; sin theta = sine of the largest principal angle between the subspaces",
+    }
+    return cb, acc
 
 
 def device_windows(reqs, metrics=16, ranks=(8, 4, 16), rel_noise=0.01):
@@ -230,6 +263,154 @@ def serving_bench(n_requests, prec_modes):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def flush_caches(buf):
+    """Writes a 1 GiB device buffer: evicts the 256 MB last-level cache and
+    the L2s, so that the next kernel reads its inputs from HBM."""
+    buf.fill_(1.0)
+
+
+def run_workload(M, torch, X, shape, ranks, p, sweeps, seed, steps, warmup, cold_sweeps=10):
+    """One workload: `warmup` untimed steps, `steps` timed whole steps
+    (coin toss + layouts, HOSVD, sweeps, core; each window's status read
+    before the next), per-phase times over PHASE_WINDOWS further windows,
+    and the sparse passes timed warm (inside the timed steps, one launch in
+    TIMING_EVERY) and cold (one sweep after each flush of the caches)."""
+    dec = M.Decomposition(shape, ranks, p)
+
+    def step(win):
+        dec.sample(X, seed, win)
+        dec.hosvd()
+        for _ in range(sweeps):
+            dec.sweep()
+        dec.core()
+        st = dec.status()[0]
+        if st != 0:
+            raise SystemExit(f"device status {st} ({M.status_string(st)}) in window {win}")
+
+    for w in range(warmup):
+        step(w)
+    torch.cuda.synchronize()
+    M.timing_enable(TIMING_EVERY)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record()
+    for k in range(steps):
+        step(warmup + k)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = e0.elapsed_time(e1) / steps
+    nnz = dec.status()[1]
+    warm = {0: M.timing_read(0), 1: M.timing_read(1)}
+    M.timing_enable(0)
+
+    names = ("sample_ms", "hosvd_ms", "sweeps_ms", "core_ms")
+    per = {k: [] for k in names}
+    for wi in range(PHASE_WINDOWS):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
+        dec.sample(X, seed, 1000 + wi)
+        ev[1].record()
+        dec.hosvd()
+        ev[2].record()
+        for _ in range(sweeps):
+            dec.sweep()
+        ev[3].record()
+        dec.core()
+        ev[4].record()
+        torch.cuda.synchronize()
+        for i, k in enumerate(names):
+            per[k].append(ev[i].elapsed_time(ev[i + 1]))
+    if dec.status()[0] != 0:
+        raise SystemExit("device status after the per-phase windows")
+    phase = {k: sum(v) / len(v) for k, v in per.items()}
+    phase_range = {k: [round(min(v), 3), round(max(v), 3)] for k, v in per.items()}
+    phase["sweep_ms"] = phase["sweeps_ms"] / sweeps
+
+    # Cold: every timed sweep follows a 1 GiB write, so its sparse passes
+    # read the kept entries from HBM.
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    M.timing_enable(1)
+    for _ in range(cold_sweeps):
+        flush_caches(flush)
+        dec.sweep()
+    torch.cuda.synchronize()
+    cold = {0: M.timing_read(0), 1: M.timing_read(1)}
+    M.timing_enable(0)
+    del flush
+    if dec.status()[0] != 0:
+        raise SystemExit("device status after the cold sweeps")
+    return dec, {"ms_step": ms_step, "wall": wall, "nnz": nnz, "phase": phase,
+                 "phase_range": phase_range, "warm": warm, "cold": cold, "per": per}
+
+
+def pass_roofline(shape, ranks, nnz, h, r):
+    """Roofline of the slower sparse pass, timed cold; warm beside it."""
+    d = len(shape)
+    MH = int(np.prod(shape[:h]))
+    MT = int(np.prod(shape[h:]))
+    KT = int(np.prod(ranks[h:]))
+    KH = int(np.prod(ranks[:h]))
+    alg = {0: nnz * 8 + MH * KT * 4 + (MH + 1) * 4, 1: nnz * 8 + MT * KH * 4 + (MT + 1) * 4}
+    name = {0: "ttm_head_rows", 1: "ttm_tail_cols"}
+    out = {}
+    for w in (0, 1):
+        ms_c, n_c = r["cold"][w]
+        ms_w, n_w = r["warm"][w]
+        if n_c == 0 or n_w == 0:
+            raise SystemExit("a sparse pass was not timed")
+        out[w] = {"cold_us": ms_c / n_c * 1e3, "warm_us": ms_w / n_w * 1e3, "n_cold": n_c, "n_warm": n_w,
+                  "bytes": alg[w]}
+    dom = max(out, key=lambda w: out[w]["cold_us"])
+    o = out[dom]
+    achieved = o["bytes"] / (o["cold_us"] * 1e-6) / 1e9
+    del d
+    return {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic_from_profiles(name[dom]),
+        "kernel": name[dom], "timing": "cold (1 GiB written before each timed sweep)",
+        "avg_launch_us": round(o["cold_us"], 2), "launches": o["n_cold"],
+        "algorithmic_bytes_per_launch": int(o["bytes"]),
+        "warm": {"avg_launch_us": round(o["warm_us"], 2),
+                 "achieved_GBs": round(o["bytes"] / (o["warm_us"] * 1e-6) / 1e9, 1),
+                 "launches": o["n_warm"], "sampled_1_in": TIMING_EVERY},
+        "other_pass": {name[w]: {"cold_us": round(v["cold_us"], 2), "warm_us": round(v["warm_us"], 2),
+                                 "cold_GBs": round(v["bytes"] / (v["cold_us"] * 1e-6) / 1e9, 1),
+                                 "algorithmic_bytes_per_launch": int(v["bytes"])}
+                       for w, v in out.items() if w != dom},
+    }
+
+
+def host_measures(X_np, G, factors):
+    """e = ||X - G x_n A_n|| / ||X|| and e' = ||X - X x_n A_n A_n^T|| / ||X||
+    for orthonormal float64 factors, in float64 on the host."""
+    X = np.asarray(X_np, np.float64)
+    nx2 = float(np.sum(X * X))
+    P = X
+    for n, A in enumerate(factors):
+        P = np.moveaxis(np.tensordot(np.asarray(A, np.float64), P, axes=(0, n)), 0, n)
+    e = math.sqrt(max(0.0, nx2 - 2.0 * float(np.sum(P * G)) + float(np.sum(G * G))) / nx2)
+    e2 = math.sqrt(max(0.0, nx2 - float(np.sum(P * P))) / nx2)
+    return e, e2
+
+
+def sin_theta_host(A_ref, A):
+    A_ref, A = np.asarray(A_ref, np.float64), np.asarray(A, np.float64)
+    return float(np.linalg.norm(A - A_ref @ (A_ref.T @ A), 2))
+
+
 def main():
     args = parse()
     if args.pmc_summary:
@@ -253,71 +434,26 @@ def main():
     shape, ranks, p, sweeps = (128, 16, 16384), (8, 4, 16), args.p, args.sweeps
     X_np, _ = synth.workload2(shape)
     X = torch.from_numpy(X_np).cuda()
-    dec = M.Decomposition(shape, ranks, p)
-
-    def step(win):
-        dec.sample(X, args.seed, win)
-        dec.hosvd()
-        for _ in range(sweeps):
-            dec.sweep()
-        dec.core()
-        # Each window's device status is read before its factors are used
-        # (mach_read_status waits for the window's work on the stream).
-        st = dec.status()[0]
-        if st != 0:
-            raise SystemExit(f"device status {st} ({M.status_string(st)}) in window {win}")
-
-    for w in range(args.warmup):
-        step(w)
-    torch.cuda.synchronize()
-    st, nnz, _ = dec.status()
-    if st != 0:
-        raise SystemExit(f"device status {st} ({M.status_string(st)}) after warmup")
-
-    # Timed region: K whole steps, kernel timing of the sparse passes on (one
-    # launch in every TIMING_EVERY of each kind, so that the event markers do
-    # not weigh on the step time).
-    M.timing_enable(TIMING_EVERY)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    e0.record()
-    for k in range(args.steps):
-        step(args.warmup + k)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_total = e0.elapsed_time(e1)
-    ms_step = ms_total / args.steps
-    st, nnz, _ = dec.status()
-    if st != 0:
-        raise SystemExit(f"device status {st} ({M.status_string(st)})")
-    rows_ms, rows_n = M.timing_read(0)
-    cols_ms, cols_n = M.timing_read(1)
-    M.timing_enable(0)
-
-    # Per-phase times, averaged over PHASE_WINDOWS extra windows (not part of
-    # the timed region; the sweep time varies from window to window).
-    names = ("sample_ms", "hosvd_ms", "sweeps_ms", "core_ms")
-    per = {k: [] for k in names}
-    for wi in range(PHASE_WINDOWS):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-        ev[0].record()
-        dec.sample(X, args.seed, 1000 + wi)
-        ev[1].record()
-        dec.hosvd()
-        ev[2].record()
-        for _ in range(sweeps):
-            dec.sweep()
-        ev[3].record()
-        dec.core()
-        ev[4].record()
-        torch.cuda.synchronize()
-        for i, k in enumerate(names):
-            per[k].append(ev[i].elapsed_time(ev[i + 1]))
-    phase = {k: sum(v) / len(v) for k, v in per.items()}
-    phase_range = {k: [round(min(v), 3), round(max(v), 3)] for k, v in per.items()}
-    phase["sweep_ms"] = phase["sweeps_ms"] / sweeps
+    dec, r = run_workload(M, torch, X, shape, ranks, p, sweeps, args.seed, args.steps, args.warmup)
+    nnz = r["nnz"]
+    h, _ = M.layout_info(shape)
+    value = nnz * sweeps / (r["ms_step"] / 1e3)
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "nnz/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "monitoring-128x16x16384-f32", "p": p, "ranks": list(ranks),
+                   "sweeps": sweeps, "nnz": nnz,
+                   "step": "coin toss + layouts + HOSVD + sweeps + core",
+                   "eigensolve_dtype": "f64"},
+        "wall_s_timed": round(r["wall"], 3),
+        "phases_ms": {k: round(v, 3) for k, v in r["phase"].items()},
+        "phases_ms_range": r["phase_range"],
+        "phases_windows": PHASE_WINDOWS,
+        "sweep_only_nnz_per_s": round(nnz / (r["phase"]["sweep_ms"] / 1e3), 1),
+        "roofline": pass_roofline(shape, ranks, nnz, h, r),
+    }
     # The coin toss + layouts with stream (tick-keyed) coins against window
     # coins on the same window, 10 calls each (not part of the timed region).
     coin_ms = {}
@@ -334,54 +470,14 @@ def main():
         coin_ms[kind] = ev2[0].elapsed_time(ev2[1]) / 10
     if dec.status()[0] != 0:
         raise SystemExit("device status after the coin comparison")
-    nnz_w, KT, KH = dec.status()[1], ranks[2], ranks[0] * ranks[1]
-    MH, MT = shape[0] * shape[1], shape[2]
-
-    passes = {
-        "ttm_head_rows": (rows_ms, rows_n, nnz * 8 + MH * KT * 4 + (MH + 1) * 4),
-        "ttm_tail_cols": (cols_ms, cols_n, nnz * 8 + MT * KH * 4 + (MT + 1) * 4),
-    }
-    if min(v[1] for v in passes.values()) == 0:
-        raise SystemExit("no sparse pass was timed")
-    dom = max(passes, key=lambda k: passes[k][0] / passes[k][1])
-    ms_k, n_k, bytes_k = passes[dom]
-    avg_s = ms_k / n_k / 1e3
-    achieved = bytes_k / avg_s / 1e9
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic_from_profiles(dom),
-        "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_k, "sampled_1_in": TIMING_EVERY,
-        "algorithmic_bytes_per_launch": int(bytes_k),
-        "other_pass": {k: {"avg_launch_us": round(v[0] / v[1] * 1e3, 2),
-                           "achieved_GBs": round(v[2] / (v[0] / v[1] / 1e3) / 1e9, 1)}
-                       for k, v in passes.items() if k != dom},
-    }
-    value = nnz * sweeps / (ms_step / 1e3)
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "nnz/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "monitoring-128x16x16384-f32", "p": p, "ranks": list(ranks),
-                   "sweeps": sweeps, "nnz": nnz,
-                   "step": "coin toss + layouts + HOSVD + sweeps + core",
-                   "eigensolve_dtype": "f64"},
-        "wall_s_timed": round(wall, 3),
-        "phases_ms": {k: round(v, 3) for k, v in phase.items()},
-        "phases_ms_range": phase_range,
-        "phases_windows": PHASE_WINDOWS,
-        "stream_coins": {"sample_ms_window_coins": round(coin_ms["window"], 4),
-                         "sample_ms_tick_coins": round(coin_ms["ticks"], 4),
-                         "input_GBs_tick_coins": round(X.numel() * 4 / (coin_ms["ticks"] / 1e3) / 1e9, 1),
-                         "note": "coin toss + compaction + layouts of the window; tick coins "
-                                 "keyed on (seed, series, absolute tick)"},
-        "sweep_only_nnz_per_s": round(nnz / (phase["sweep_ms"] / 1e3), 1),
-        "roofline": roofline,
-    }
-    # Mixed precision on the same window: 20 sweeps after HOSVD with bfloat16
+    out["stream_coins"] = {"sample_ms_window_coins": round(coin_ms["window"], 4),
+                           "sample_ms_tick_coins": round(coin_ms["ticks"], 4),
+                           "input_GBs_tick_coins": round(X.numel() * 4 / (coin_ms["ticks"] / 1e3) / 1e9, 1),
+                           "note": "coin toss + compaction + layouts of the window; tick coins "
+                                   "keyed on (seed, series, absolute tick)"}
+    # Mixed precision on the same window: sweeps after HOSVD with bfloat16
     # factor entries in the sparse TTM, against the float32 run of the last
-    # per-phase window above.
+    # per-phase window.
     A32 = [a.clone() for a in dec.factors]
     fit32 = float(dec.fit.item())
     last_win = 1000 + PHASE_WINDOWS - 1
@@ -396,18 +492,31 @@ def main():
     torch.cuda.synchronize()
     if dec.status()[0] != 0:
         raise SystemExit("device status after the bfloat16 sweeps")
-    import numpy as np
-    sin_max = 0.0
-    for a32, abf in zip(A32, dec.factors):
-        a32, abf = a32.cpu().numpy(), abf.cpu().numpy()
-        sin_max = max(sin_max, float(np.linalg.norm(abf - a32 @ (a32.T @ abf), 2)))
+    sin_max = max(sin_theta_host(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(A32, dec.factors))
     out["precision"] = {
         "window": last_win,
-        "f32": {"sweep_ms": round(per["sweeps_ms"][-1] / sweeps, 4), "fit": fit32},
+        "f32": {"sweep_ms": round(r["per"]["sweeps_ms"][-1] / sweeps, 4), "fit": fit32},
         "bf16": {"sweep_ms": round(eb0.elapsed_time(eb1) / sweeps, 4), "fit": float(dec.fit.item()),
                  "max_sin_theta_vs_f32": sin_max},
         "note": "bf16 = sparse-TTM factor entries rounded to bfloat16, float32 sums, float64 eigensolve",
     }
+    # The benchmarked window once more (window 0: HOSVD + sweeps + core) for
+    # the accuracy comparison with the oracle in the CPU leg.
+    dec.sample(X, args.seed, 0)
+    dec.hosvd()
+    for _ in range(sweeps):
+        dec.sweep()
+    dec.core()
+    if dec.status()[0] != 0:
+        raise SystemExit("device status of the accuracy window")
+    gpu_factors = [a.cpu().numpy() for a in dec.factors]
+    gpu_core = dec.G.cpu().numpy()
+    gpu_fit = float(dec.fit.item())
+    del dec
+    torch.cuda.synchronize()
+
+    if not args.no_voxel:
+        out["voxel"] = voxel_bench(M, torch, synth, args)
     if args.copy_mib > 0:
         a = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -418,8 +527,35 @@ def main():
     if args.serve_requests > 0:
         out["serving"] = serving_bench(args.serve_requests, [("bf16", M.MACH_BF16)])
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(X_np, p, args.seed, ranks, sweeps, args.cpu_sweeps, nnz)
+        cb, acc = cpu_baseline(X_np, p, args.seed, ranks, sweeps, nnz, gpu_factors, gpu_core, gpu_fit)
+        out["cpu_baseline"] = cb
+        out["accuracy"] = acc
     print(json.dumps(out), flush=True)
+
+
+def voxel_bench(M, torch, synth, args):
+    """The 4-way voxel workload 64x64x64x256 (float32, core 10^4 with a
+    geometrically decaying spectrum + 1 % noise) at p = 0.05, rank
+    (10,10,10,10), 10 sweeps: whole-step throughput, phases and the sparse
+    passes' roofline, as for the monitoring window."""
+    shape, ranks, p, sweeps, seed = (64, 64, 64, 256), (10, 10, 10, 10), 0.05, 10, 20263
+    X_np, _ = synth.workload3(shape)
+    X = torch.from_numpy(X_np).cuda()
+    del X_np
+    dec, r = run_workload(M, torch, X, shape, ranks, p, sweeps, seed, max(2, args.steps // 2), 1)
+    h, _ = M.layout_info(shape)
+    nnz = r["nnz"]
+    out = {"workload": "voxel-64x64x64x256-f32", "p": p, "ranks": list(ranks), "sweeps": sweeps,
+           "nnz": nnz, "value": round(nnz * sweeps / (r["ms_step"] / 1e3), 1), "unit": "nnz/s",
+           "ms_per_step": round(r["ms_step"], 3),
+           "phases_ms": {k: round(v, 3) for k, v in r["phase"].items()},
+           "phases_ms_range": r["phase_range"],
+           "sweep_only_nnz_per_s": round(nnz / (r["phase"]["sweep_ms"] / 1e3), 1),
+           "roofline": pass_roofline(shape, ranks, nnz, h, r)}
+    out["roofline"]["traffic"] = None
+    del dec, X
+    torch.cuda.synchronize()
+    return out
 
 
 if __name__ == "__main__":

@@ -309,6 +309,10 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   for (int k = 0; k < d; ++k) S.af16[k] = take((size_t)I[k] * 16 * 2);
   S.TH = take((size_t)si.MH * S.KT * 4);
   S.TT = take((size_t)si.MT * S.KH * 4);
+  if (d - h == 1 && (size_t)I[d - 1] * 16 * 4 > kTiledFactorBytes) {
+    const size_t nt = (I[d - 1] + kTileTicksMin - 1) / kTileTicksMin;
+    S.tpart = take(nt * si.MH * 16 * 4);
+  }
   for (int k = 0; k < d; ++k) {
     ModePlan& m = S.mp[k];
     if (m.contract_mode >= 0) m.ybuf = take((size_t)m.I * m.K * 4);

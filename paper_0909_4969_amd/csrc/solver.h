@@ -46,6 +46,11 @@ constexpr uint32_t kBlock = 64;          // subspace block for sides > kSmallEig
 constexpr uint32_t kSredGram = 0, kSredCtc = 4096, kSredTall = 4096 + 768, kSredElems = 4096 + 768 + 256;
 constexpr uint32_t kSplitK = 256;        // summation slice of the split products by G
 constexpr uint32_t kMfmaGramMaxRows = 1024;  // row-side HOSVD Grams on MFMA up to this side
+// Tiled head-row pass: the tail factor is tiled when its float32 copy (16
+// columns) exceeds kTiledFactorBytes; tiles span kTileTicksMin..kTileTicksMax
+// ticks.
+constexpr uint32_t kTiledFactorBytes = 16384;
+constexpr uint32_t kTileTicksMin = 128, kTileTicksMax = 512;
 
 // Status region: int32 status word at +0, int32 tags[16] at +16 (eigen
 // warm-start tags of modes 0..7, then kTagRR, kTagCold, kTagDone), int32
@@ -69,6 +74,9 @@ struct SolverLayout {
   size_t pv, pi;                         // column-max partials (1024 x 16)
   size_t tags;                           // int32 tags of warm starts and early exits (16)
   size_t sred;                           // float64 reduced partials (kSredElems)
+  // Tiled head-row pass (one tail mode whose factor is too large for LDS):
+  // float32 partial rows, tiles x MH x 16; 0 when the pass is not tiled.
+  size_t tpart;
   // A second copy of the scratch above (G .. sred), used by the HOSVD of the
   // last mode when it runs on its own stream beside the other modes; 0 when
   // there is none (d == 1).

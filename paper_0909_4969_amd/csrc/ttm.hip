@@ -262,6 +262,194 @@ __global__ __launch_bounds__(256) void k_spc(SpcArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Head-row pass with one contracted tail mode whose factor is too large for
+// LDS (a long time mode): TH[r, :] = sum over the kept entries (r, c) of
+// v * A[c, :].  The rows x columns plane is cut into tiles of RB head rows
+// by TC tail columns.  A workgroup copies the TC factor rows of its tile into
+// LDS once, so a factor row is fetched from L2 once per tile instead of once
+// per kept entry.  Each row of the tile belongs to LPE lanes (lane `quad`
+// owns inner columns 4 quad .. 4 quad + 3); its entries with c0 <= c < c1
+// (found by two bitmap ranks) are loaded by those lanes together, kLoad per
+// lane and all in flight at once, then passed round the LPE lanes by DPP
+// quad permutes, and each entry's factor row is read from LDS.  Every tile
+// writes one partial row per head row, and k_rows_tiled_sum adds the
+// partials of a row in tile order: the result does not depend on
+// scheduling, and no float atomics are used.
+// ---------------------------------------------------------------------------
+struct TiledArgs {
+  const Entry* ent;            // kept entries in linear-index order
+  const uint64_t* bitmap;
+  const uint32_t* wrank;
+  uint32_t MH, MT;
+  const void* F;               // tail factor copy, row stride 16 (float32 or bfloat16)
+  uint32_t Rin;                // used factor columns
+  uint32_t TC, nT, RB;         // ticks per tile, tiles, rows per block
+  float4* part;                // nT x MH x LPE float4 partial rows
+  float* out;                  // TH, row stride K
+  uint32_t K;
+  const SampleHdr* hdr;
+  const int32_t* st_solver;
+};
+
+// Kept entries with linear index below l (bit_rank, without reading the
+// word past the bitmap when l is a multiple of 64).
+__device__ __forceinline__ uint32_t rank_below(const uint64_t* bitmap, const uint32_t* wrank,
+                                               uint32_t l) {
+  return (l & 63u) ? bit_rank(bitmap, wrank, l) : wrank[l >> 6];
+}
+
+// Value of lane (lane & ~(LPE-1)) + src of the LPE-lane group (LPE = 1, 2, 4).
+template <int LPE>
+__device__ __forceinline__ uint32_t group_bcast(uint32_t x, int src) {
+  if constexpr (LPE == 1) {
+    return x;
+  } else if constexpr (LPE == 2) {
+    // quad_perm(src, src, 2 + src, 2 + src)
+    return src == 0 ? (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xA0, 0xf, 0xf, false)
+                    : (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xF5, 0xf, 0xf, false);
+  } else {
+    // quad_perm(src, src, src, src)
+    switch (src) {
+      case 0: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x00, 0xf, 0xf, false);
+      case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x55, 0xf, 0xf, false);
+      case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xAA, 0xf, 0xf, false);
+      default: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xFF, 0xf, 0xf, false);
+    }
+  }
+}
+
+constexpr int kLoad = 16;   // entry loads in flight per lane
+
+template <int RI, int BF>
+__global__ __launch_bounds__(256) void k_rows_tiled(TiledArgs a) {
+  if (a.hdr->status != 0 || *a.st_solver != 0) return;
+  constexpr int LPE = RI / 4;
+  extern __shared__ float4 ftile[];          // TC rows x LPE quads
+  const uint32_t tile = blockIdx.x, blk = blockIdx.y;
+  const uint32_t c0 = tile * a.TC, c1 = min(a.MT, c0 + a.TC);
+  const int quad = threadIdx.x & (LPE - 1);
+  const uint32_t r_lo = blk * a.RB, r_hi = min(a.MH, r_lo + a.RB);
+  // Ranks of the first rows are requested before the factor tile is copied.
+  uint32_t r = r_lo + threadIdx.x / LPE;
+  uint32_t lo = 0, hi = 0;
+  if (r < r_hi) {
+    lo = rank_below(a.bitmap, a.wrank, r * a.MT + c0);
+    hi = rank_below(a.bitmap, a.wrank, r * a.MT + c1);
+  }
+  const uint32_t nq = (c1 - c0) * LPE;
+  for (uint32_t e = threadIdx.x; e < nq; e += 256) ftile[e] = factor4<BF>(a.F, c0 + e / LPE, e % LPE);
+  __syncthreads();
+  const uint64_t* ent64 = reinterpret_cast<const uint64_t*>(a.ent);
+  for (; r < r_hi; r += 256 / LPE) {
+    if (r != r_lo + threadIdx.x / LPE) {
+      lo = rank_below(a.bitmap, a.wrank, r * a.MT + c0);
+      hi = rank_below(a.bitmap, a.wrank, r * a.MT + c1);
+    }
+    const uint32_t base = r * a.MT + c0;
+    // an unused slot holds (base, 0.0f): column c0 with weight 0
+    const uint64_t dummy = (uint64_t)base;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (uint32_t e0 = lo; e0 < hi; e0 += LPE * kLoad) {
+      uint64_t en[kLoad];
+#pragma unroll
+      for (int j = 0; j < kLoad; ++j) {
+        const uint32_t e = e0 + LPE * j + quad;
+        en[j] = e < hi ? ent64[e] : dummy;
+      }
+#pragma unroll
+      for (int j = 0; j < kLoad; ++j) {
+#pragma unroll
+        for (int q = 0; q < LPE; ++q) {
+          const uint32_t l = group_bcast<LPE>((uint32_t)en[j], q);
+          const float v = __uint_as_float(group_bcast<LPE>((uint32_t)(en[j] >> 32), q));
+          const float4 w = ftile[(l - base) * LPE + quad];
+          acc.x = fmaf(v, w.x, acc.x);
+          acc.y = fmaf(v, w.y, acc.y);
+          acc.z = fmaf(v, w.z, acc.z);
+          acc.w = fmaf(v, w.w, acc.w);
+        }
+      }
+    }
+    a.part[((size_t)tile * a.MH + r) * LPE + quad] = acc;
+  }
+}
+
+// TH[r, 4 q .. 4 q + 3] = sum over the tiles of the partials, one wave per
+// head row: lane (t, q) adds tiles t, t + 64/LPE, ... in order, then a fixed
+// xor butterfly adds the lanes of equal q.
+template <int RI>
+__global__ __launch_bounds__(256) void k_rows_tiled_sum(TiledArgs a) {
+  if (a.hdr->status != 0 || *a.st_solver != 0) return;
+  constexpr int LPE = RI / 4;
+  constexpr uint32_t TS = 64 / LPE;       // tile lanes per row
+  const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= a.MH) return;
+  const uint32_t lane = threadIdx.x & 63, q = lane % LPE, t0 = lane / LPE;
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  constexpr int U = 4;
+  for (uint32_t t = t0; t < a.nT; t += U * TS) {
+    float4 pv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t tt = t + u * TS;
+      pv[u] = tt < a.nT ? a.part[((size_t)tt * a.MH + r) * LPE + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s.x += pv[u].x;
+      s.y += pv[u].y;
+      s.z += pv[u].z;
+      s.w += pv[u].w;
+    }
+  }
+  for (int m = LPE; m < 64; m <<= 1) {
+    s.x += __shfl_xor(s.x, m, 64);
+    s.y += __shfl_xor(s.y, m, 64);
+    s.z += __shfl_xor(s.z, m, 64);
+    s.w += __shfl_xor(s.w, m, 64);
+  }
+  if (t0 != 0) return;
+  float* o = a.out + (size_t)r * a.K + 4 * q;
+  const float sv[4] = {s.x, s.y, s.z, s.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (4 * q + j < a.Rin) o[j] = sv[j];
+}
+
+// Rows per block: 256 / LPE (one row per lane group) when a factor row
+// copied into LDS then serves several kept entries (at least 3 expected);
+// else 0 and the gather pass is used (sparse samples).
+inline uint32_t tiled_rows_per_block(double density, int lpe) {
+  const uint32_t rb = 256u / (uint32_t)lpe;
+  return density * rb >= 3.0 ? rb : 0u;
+}
+
+template <int RI, int BF>
+hipError_t go_tiled(TiledArgs a, hipStream_t st) {
+  // Ticks per tile: the largest of 512, 256, 128 that still gives at least
+  // 1024 workgroups (or the smallest).
+  const uint32_t nrb = (a.MH + a.RB - 1) / a.RB;
+  uint32_t tc = kTileTicksMax;
+  while (tc > kTileTicksMin && (size_t)nrb * ((a.MT + tc - 1) / tc) < 1024) tc /= 2;
+  a.TC = tc;
+  a.nT = (a.MT + tc - 1) / tc;
+  const uint32_t lds = tc * (RI / 4) * 16u;
+  dim3 grid(a.nT, nrb);
+  hipEvent_t e0, e1;
+  const bool timed = timing_events(0, &e0, &e1);
+  if (timed)
+    hipExtLaunchKernelGGL((k_rows_tiled<RI, BF>), grid, dim3(256), lds, st, e0, nullptr, 0, a);
+  else
+    hipLaunchKernelGGL((k_rows_tiled<RI, BF>), grid, dim3(256), lds, st, a);
+  const uint32_t nsum = (a.MH + 3) / 4;
+  if (timed)
+    hipExtLaunchKernelGGL((k_rows_tiled_sum<RI>), dim3(nsum), dim3(256), 0, st, nullptr, e1, 0, a);
+  else
+    hipLaunchKernelGGL((k_rows_tiled_sum<RI>), dim3(nsum), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 inline int pad4(uint32_t r) { return r <= 4 ? 4 : r <= 8 ? 8 : r <= 12 ? 12 : 16; }
 
 template <int NQ, int RI, int RO, int CSC, int BF, int LF>
@@ -458,6 +646,26 @@ hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const
   a.dense_len = si.MT;
   a.hdr = sp.hdr;
   a.st_solver = (const int32_t*)(ws + SL.status);
+  const uint32_t rb = tiled_rows_per_block(density, pad_inner(a.Rin) / 4);
+  if (q == 1 && SL.tpart && rb && (si.MH + rb - 1) / rb <= 65535u) {
+    TiledArgs t{};
+    t.ent = sp.coo_l;
+    t.bitmap = sp.bitmap;
+    t.wrank = sp.wrank;
+    t.MH = si.MH;
+    t.MT = si.MT;
+    t.F = a.Ain;
+    t.Rin = a.Rin;
+    t.RB = rb;
+    t.part = (float4*)(ws + SL.tpart);
+    t.out = a.out;
+    t.K = a.K;
+    t.hdr = a.hdr;
+    t.st_solver = a.st_solver;
+    const int ri = pad_inner(a.Rin);
+    if (bf16) return ri == 4 ? go_tiled<4, 1>(t, st) : ri == 8 ? go_tiled<8, 1>(t, st) : go_tiled<16, 1>(t, st);
+    return ri == 4 ? go_tiled<4, 0>(t, st) : ri == 8 ? go_tiled<8, 0>(t, st) : go_tiled<16, 0>(t, st);
+  }
   return go_any(a, q, bf16, st);
 }
 
