@@ -352,37 +352,80 @@ struct MfmaGramArgs {
   const int32_t* st_solver;
 };
 
-template <int RB>
-__device__ __forceinline__ void mfma_stage(const MfmaGramArgs& a, uint32_t row0, uint32_t jc,
-                                           float (*M)[4096 / RB + 4]) {
-  constexpr int CW = 4096 / RB, WPR = CW / 64;
-  const int t = threadIdx.x, q = t & 3, rw = t >> 2;
-  const int r = rw / WPR, wd = rw % WPR;
-  const uint32_t i = row0 + r, j = jc + wd * 64;
-  uint64_t word = 0;
-  uint32_t base = 0;
-  if (i < a.I && j < a.J) {
-    const uint32_t qq = a.fQ.div(j);
-    const uint32_t l0 = qq * a.I * a.Q + (j - qq * a.Q) + i * a.Q;
-    word = a.bitmap[l0 >> 6];
-    base = a.wrank[l0 >> 6];
-  }
-#pragma unroll
-  for (int bb = 0; bb < 16; ++bb) {
-    const int bit = q * 16 + bb;
-    float v = 0.f;
-    if ((word >> bit) & 1ull) {
-      const uint64_t below = bit ? (word & ((~0ull) >> (64 - bit))) : 0ull;
-      v = a.coo[base + (uint32_t)__popcll(below)].v;
-    }
-    M[r][wd * 64 + bit] = v;
-  }
-}
+// Staging of one chunk (RB rows x CW = 4096 / RB columns of Xhat_(n)).
+// Each thread owns one bitmap word and 16 of its bits: the word's kept
+// values are consecutive entries of the l-ordered list from the word's
+// rank.  Two column layouts:
+//  - Q1 = false (Q a multiple of 64): 64 consecutive columns of one row are
+//    one word; thread (row r, word wd, quarter q).
+//  - Q1 = true (the last mode, Q = 1, I a multiple of 64, RB = 64): the 64
+//    rows of one column are one word; thread (column cc, quarter q).
+template <int RB, bool Q1>
+struct MfmaStage {
+  static constexpr int CW = 4096 / RB;
+  uint64_t word;
+  uint32_t base;
+  float v[16];
 
-template <int RB>
+  __device__ __forceinline__ void load_word(const MfmaGramArgs& a, uint32_t row0, uint32_t jc) {
+    const int t = threadIdx.x;
+    word = 0;
+    base = 0;
+    if constexpr (Q1) {
+      const uint32_t j = jc + (t >> 2);
+      if (j < a.J && row0 < a.I) {
+        const uint32_t l0 = j * a.I + row0;
+        word = a.bitmap[l0 >> 6];
+        base = a.wrank[l0 >> 6];
+      }
+    } else {
+      constexpr int WPR = CW / 64;
+      const int rw = t >> 2, r = rw / WPR, wd = rw % WPR;
+      const uint32_t i = row0 + r, j = jc + wd * 64;
+      if (i < a.I && j < a.J) {
+        const uint32_t qq = a.fQ.div(j);
+        const uint32_t l0 = qq * a.I * a.Q + (j - qq * a.Q) + i * a.Q;
+        word = a.bitmap[l0 >> 6];
+        base = a.wrank[l0 >> 6];
+      }
+    }
+  }
+  __device__ __forceinline__ void load_values(const MfmaGramArgs& a) {
+    const int q = threadIdx.x & 3;
+    const uint32_t below = (uint32_t)__popcll(q ? (word & ((~0ull) >> (64 - 16 * q))) : 0ull);
+    const uint32_t bits = (uint32_t)(word >> (16 * q)) & 0xffffu;
+    uint32_t r = base + below;
+#pragma unroll
+    for (int bb = 0; bb < 16; ++bb) {
+      const bool kept = (bits >> bb) & 1u;
+      v[bb] = kept ? a.coo[r].v : 0.f;
+      r += kept ? 1u : 0u;
+    }
+  }
+  __device__ __forceinline__ void store(float (*M)[CW + 4]) const {
+    const int t = threadIdx.x, q = t & 3;
+    if constexpr (Q1) {
+      const int cc = t >> 2;
+#pragma unroll
+      for (int bb = 0; bb < 16; ++bb) M[q * 16 + bb][cc] = v[bb];
+    } else {
+      constexpr int WPR = CW / 64;
+      const int rw = t >> 2, r = rw / WPR, wd = rw % WPR;
+#pragma unroll
+      for (int bb = 0; bb < 16; ++bb) M[r][wd * 64 + q * 16 + bb] = v[bb];
+    }
+  }
+};
+
+// Tiles of an RB x RB block: TB x TB 16 x 16 tiles.  With at least four
+// tiles every wave owns a quarter of them over all columns; a single tile
+// (RB = 16) is shared by the four waves, each taking every fourth group of
+// 4 columns, and their sums are added in wave order.
+template <int RB, bool Q1>
 __global__ __launch_bounds__(256) void k_gram_mfma(MfmaGramArgs a) {
   if (a.hdr->status != 0 || *a.st_solver != 0) return;
   constexpr int CW = 4096 / RB, TB = RB / 16, KS = CW / 4;
+  constexpr int NT = TB * TB, TPW = NT >= 4 ? NT / 4 : 1, KSPLIT = NT >= 4 ? 1 : 4;
   __shared__ float Ma[RB][CW + 4];
   __shared__ float Mb[RB][CW + 4];
   uint32_t by = 0;
@@ -391,63 +434,100 @@ __global__ __launch_bounds__(256) void k_gram_mfma(MfmaGramArgs a) {
   const bool diag = bx == by;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  v4f acc[TB][TB];
-  double dacc[TB][TB][4];
+  v4f acc[TPW];
+  double dacc[TPW][4];
 #pragma unroll
-  for (int x = 0; x < TB; ++x)
+  for (int u = 0; u < TPW; ++u) {
+    acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int y = 0; y < TB; ++y) {
-      acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dacc[x][y][v] = 0.0;
-    }
-  const uint32_t c0 = blockIdx.y * a.cps;
-  for (uint32_t c = c0; c < c0 + a.cps; ++c) {
-    const uint32_t jc = c * CW;
-    if (jc >= a.J) break;
-    __syncthreads();
-    mfma_stage<RB>(a, bx * RB, jc, Ma);
-    if (!diag) mfma_stage<RB>(a, by * RB, jc, Mb);
-    __syncthreads();
-    float (*B)[CW + 4] = diag ? Ma : Mb;
-    for (int ks = w; ks < KS; ks += 4) {
-      float av[TB], bv[TB];
-#pragma unroll
-      for (int x = 0; x < TB; ++x) {
-        av[x] = Ma[x * 16 + li][ks * 4 + lk];
-        bv[x] = B[x * 16 + li][ks * 4 + lk];
-      }
-#pragma unroll
-      for (int x = 0; x < TB; ++x)
-#pragma unroll
-        for (int y = 0; y < TB; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc[x][y], 0, 0, 0);
-    }
-#pragma unroll
-    for (int x = 0; x < TB; ++x)
-#pragma unroll
-      for (int y = 0; y < TB; ++y) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dacc[x][y][v] += (double)acc[x][y][v];
-        acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
-      }
+    for (int v = 0; v < 4; ++v) dacc[u][v] = 0.0;
   }
-  // Wave sums in order 0..3 through LDS (reusing the staging buffers).
+  const uint32_t c0 = blockIdx.y * a.cps;
+  uint32_t c1 = c0 + a.cps;
+  const uint32_t nchunk = (a.J + CW - 1) / CW;
+  if (c1 > nchunk) c1 = nchunk;
+  // Software pipeline: the values of chunk c + 1 and the words of chunk
+  // c + 2 are requested while chunk c is multiplied.
+  MfmaStage<RB, Q1> sa, sb;
+  uint64_t wa2 = 0, wb2 = 0;
+  uint32_t ba2 = 0, bb2 = 0;
+  if (c0 < c1) {
+    sa.load_word(a, bx * RB, c0 * CW);
+    if (!diag) sb.load_word(a, by * RB, c0 * CW);
+    sa.load_values(a);
+    if (!diag) sb.load_values(a);
+    if (c0 + 1 < c1) {
+      MfmaStage<RB, Q1> t;
+      t.load_word(a, bx * RB, (c0 + 1) * CW);
+      wa2 = t.word;
+      ba2 = t.base;
+      if (!diag) {
+        t.load_word(a, by * RB, (c0 + 1) * CW);
+        wb2 = t.word;
+        bb2 = t.base;
+      }
+    }
+  }
+  for (uint32_t c = c0; c < c1; ++c) {
+    __syncthreads();
+    sa.store(Ma);
+    if (!diag) sb.store(Mb);
+    __syncthreads();
+    if (c + 1 < c1) {
+      sa.word = wa2;
+      sa.base = ba2;
+      sa.load_values(a);
+      if (!diag) {
+        sb.word = wb2;
+        sb.base = bb2;
+        sb.load_values(a);
+      }
+      if (c + 2 < c1) {
+        MfmaStage<RB, Q1> t;
+        t.load_word(a, bx * RB, (c + 2) * CW);
+        wa2 = t.word;
+        ba2 = t.base;
+        if (!diag) {
+          t.load_word(a, by * RB, (c + 2) * CW);
+          wb2 = t.word;
+          bb2 = t.base;
+        }
+      }
+    }
+    float (*B)[CW + 4] = diag ? Ma : Mb;
+    for (int ks = (KSPLIT > 1 ? w : 0); ks < KS; ks += KSPLIT) {
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int t = (NT >= 4 ? w * TPW : 0) + u, x = t / TB, y = t % TB;
+        const float av = Ma[x * 16 + li][ks * 4 + lk];
+        const float bv = B[y * 16 + li][ks * 4 + lk];
+        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[u], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dacc[u][v] += (double)acc[u][v];
+      acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+  // Tiles to LDS (reusing the staging buffers): each wave writes its own
+  // tiles; a shared tile is added up in wave order 0..3.
   __syncthreads();
   double* red = reinterpret_cast<double*>(&Ma[0][0]);
   static_assert(sizeof(Ma) + sizeof(Mb) >= RB * RB * sizeof(double), "reduction buffer");
-  for (int ww = 0; ww < 4; ++ww) {
-    if (w == ww) {
+  for (int ww = 0; ww < KSPLIT; ++ww) {
+    if (KSPLIT == 1 || w == ww) {
 #pragma unroll
-      for (int x = 0; x < TB; ++x)
+      for (int u = 0; u < TPW; ++u) {
+        const int t = (NT >= 4 ? w * TPW : 0) + u, x = t / TB, y = t % TB;
 #pragma unroll
-        for (int y = 0; y < TB; ++y)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = x * 16 + lk * 4 + v, col = y * 16 + li;
-            double* p = red + row * RB + col;
-            *p = (ww == 0) ? dacc[x][y][v] : *p + dacc[x][y][v];
-          }
+        for (int v = 0; v < 4; ++v) {
+          const int row = x * 16 + lk * 4 + v, col = y * 16 + li;
+          double* p = red + row * RB + col;
+          *p = (ww == 0) ? dacc[u][v] : *p + dacc[u][v];
+        }
+      }
     }
     __syncthreads();
   }
@@ -455,26 +535,33 @@ __global__ __launch_bounds__(256) void k_gram_mfma(MfmaGramArgs a) {
   for (int e = threadIdx.x; e < RB * RB; e += 256) out[e] = red[e];
 }
 
+// G from the slice partials, one wave per entry of the upper triangle:
+// lane s adds slices s, s + 64, ... in order, a fixed xor butterfly adds
+// the lanes, and the entry is written to both triangles.
 template <int RB>
-__global__ void k_gram_mfma_reduce(const double* __restrict__ part, uint32_t nslice, uint32_t nblk,
-                                   uint32_t I, double* __restrict__ G, const SampleHdr* hdr,
-                                   const int32_t* st_solver) {
+__global__ __launch_bounds__(256) void k_gram_mfma_reduce(const double* __restrict__ part, uint32_t nslice,
+                                                          uint32_t nblk, uint32_t I, double* __restrict__ G,
+                                                          const SampleHdr* hdr, const int32_t* st_solver) {
   if (hdr->status != 0 || *st_solver != 0) return;
-  const uint32_t e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= I * I) return;
-  uint32_t x = e / I, y = e % I;
-  uint32_t bx = x / RB, by = y / RB, xx = x % RB, yy = y % RB;
-  if (bx > by) {
-    uint32_t t = bx; bx = by; by = t;
-    t = xx; xx = yy; yy = t;
-  }
-  const uint32_t blk = by * (by + 1) / 2 + bx;
+  const uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (e >= nblk * RB * RB) return;
+  const uint32_t blk = e / (RB * RB), xx = (e / RB) % RB, yy = e % RB;
+  uint32_t by = 0;
+  while ((by + 1) * (by + 2) / 2 <= blk) ++by;
+  const uint32_t bx = blk - by * (by + 1) / 2;
+  const uint32_t x = bx * RB + xx, y = by * RB + yy;
+  if (x >= I || y >= I || (bx == by && xx > yy)) return;
   double acc = 0.0;
-  for (uint32_t s = 0; s < nslice; ++s) acc += part[((size_t)s * nblk + blk) * RB * RB + xx * RB + yy];
-  G[e] = acc;
+  for (uint32_t sl = lane; sl < nslice; sl += 64) acc += part[((size_t)sl * nblk + blk) * RB * RB + xx * RB + yy];
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m, 64);
+  if (lane == 0) {
+    G[(size_t)x * I + y] = acc;
+    G[(size_t)y * I + x] = acc;
+  }
 }
 
-template <int RB>
+template <int RB, bool Q1>
 hipError_t gram_mfma_run(MfmaGramArgs a, double* G, size_t part_elems, hipStream_t st) {
   constexpr uint32_t CW = 4096 / RB;
   a.nb = (a.I + RB - 1) / RB;
@@ -487,9 +574,10 @@ hipError_t gram_mfma_run(MfmaGramArgs a, double* G, size_t part_elems, hipStream
   if (nslice < 1) nslice = 1;
   a.cps = (chunks + nslice - 1) / nslice;
   nslice = (chunks + a.cps - 1) / a.cps;
-  hipLaunchKernelGGL((k_gram_mfma<RB>), dim3(a.nblk, nslice), dim3(256), 0, st, a);
-  hipLaunchKernelGGL((k_gram_mfma_reduce<RB>), dim3((a.I * a.I + 255) / 256), dim3(256), 0, st, a.part,
-                     nslice, a.nblk, a.I, G, a.hdr, a.st_solver);
+  hipLaunchKernelGGL((k_gram_mfma<RB, Q1>), dim3(a.nblk, nslice), dim3(256), 0, st, a);
+  const uint32_t nent = a.nblk * RB * RB;
+  hipLaunchKernelGGL((k_gram_mfma_reduce<RB>), dim3((nent + 3) / 4), dim3(256), 0, st, a.part, nslice,
+                     a.nblk, a.I, G, a.hdr, a.st_solver);
   return hipGetLastError();
 }
 
@@ -567,7 +655,8 @@ hipError_t launch_gram_xhat(const ShapeInfo& si, const SparsePtrs& sp, const Sol
   a.part = (double*)(ws + SL.Gpart);
   a.st_solver = (const int32_t*)(ws + SL.status);
   a.hdr = sp.hdr;
-  if (!a.kside && a.Q % 64 == 0 && a.I <= kMfmaGramMaxRows) {
+  const bool q1 = a.Q == 1 && a.I % 64 == 0;   // the last mode, 64-aligned
+  if (!a.kside && (a.Q % 64 == 0 || q1) && a.I <= kMfmaGramMaxRows) {
     MfmaGramArgs m{};
     m.bitmap = sp.bitmap;
     m.wrank = sp.wrank;
@@ -580,9 +669,10 @@ hipError_t launch_gram_xhat(const ShapeInfo& si, const SparsePtrs& sp, const Sol
     m.hdr = sp.hdr;
     m.st_solver = a.st_solver;
     double* G = (double*)(ws + SL.G);
-    if (a.I <= 16) return gram_mfma_run<16>(m, G, SL.Gpart_elems, st);
-    if (a.I <= 32) return gram_mfma_run<32>(m, G, SL.Gpart_elems, st);
-    return gram_mfma_run<64>(m, G, SL.Gpart_elems, st);
+    if (q1) return gram_mfma_run<64, true>(m, G, SL.Gpart_elems, st);
+    if (a.I <= 16) return gram_mfma_run<16, false>(m, G, SL.Gpart_elems, st);
+    if (a.I <= 32) return gram_mfma_run<32, false>(m, G, SL.Gpart_elems, st);
+    return gram_mfma_run<64, false>(m, G, SL.Gpart_elems, st);
   }
   MaskedLoad ld{sp.bitmap, sp.wrank, sp.coo_l};
   return gram_run(a, ld, (double*)(ws + SL.G), SL.Gpart_elems, st);
