@@ -120,8 +120,8 @@ mach_status mach_sample_ticks(const mach_shape* s, mach_dtype x_dtype, const voi
                               uint64_t nnz_cap, void* stream);
 
 /* Bytes of the solver workspace for shape s and ranks R_1..R_d (host array
- * of d int32).  prec is the sparse-TTM factor precision mach_hooi_sweep
- * will be called with (MACH_F32 or MACH_BF16; the workspace serves both).
+ * of d int32).  prec is the precision mach_hooi_sweep will be called with
+ * (MACH_F32, MACH_BF16 or MACH_FP8E4M3; the workspace serves all three).
  * Returns 0 if the arguments are invalid or prec is not supported. */
 size_t mach_solver_workspace_bytes(const mach_shape* s, const int32_t* ranks,
                                    mach_dtype prec, uint64_t nnz_cap);
@@ -146,12 +146,22 @@ mach_status mach_hosvd(const void* ws_sample, uint64_t nnz_cap, const mach_shape
 
 /* One HOOI sweep (Alg. 2, one pass of the REPEAT body) over modes
  * first_mode..d-1 in order, each update seen by the next.  For mode n:
- * Y = Xhat x_{k != n} A^(k)T (sparse tensor-times-matrix chain; factor
- * entries read as float32 for prec = MACH_F32 or rounded to bfloat16 for
- * prec = MACH_BF16, products and sums in float32 either way), the Gram of
- * Y_(n) on its smaller side, its top R_n eigenvectors in float64, and (for
- * the column-side Gram) back-projection and float64 re-orthonormalisation.
- * Other prec values return MACH_EUNSUPPORTED.
+ * Y = Xhat x_{k != n} A^(k)T (sparse tensor-times-matrix chain), the Gram
+ * of Y_(n) on its smaller side on MFMA, its top R_n eigenvectors in
+ * float64, and (for the column-side Gram) back-projection and float64
+ * re-orthonormalisation.  prec selects the arithmetic of the first two:
+ *   MACH_F32      factor entries and Gram inputs float32;
+ *   MACH_BF16     factor entries of the sparse passes and the Gram's inputs
+ *                 rounded to bfloat16 (nearest even);
+ *   MACH_FP8E4M3  factor entries as for MACH_BF16, the Gram's inputs in OCP
+ *                 float8 e4m3 (nearest even, saturating at 448), each
+ *                 staged tile of rows x summation indices scaled by its
+ *                 largest magnitude / 448;
+ * products and sums in float32 (the Gram over runs of 32 summation
+ * indices, then float64) in every case.  Other prec values return
+ * MACH_EUNSUPPORTED.  A short column-side mode (I_n <= 128,
+ * 16 <= K_n <= 64, R_n <= 8) forms no Gram: its factor comes from a block
+ * subspace iteration on Y Y^T in float64.
  * A_dev (host array of d device pointers, I_n x R_n float64) is read and
  * the updated factors written back.  If fit_dev is not NULL, the device
  * double it points to receives 1 - ||Xhat - G x A|| / ||Xhat|| after the

@@ -497,7 +497,7 @@ size_t mach_solver_workspace_bytes(const mach_shape* s, const int32_t* ranks, ma
   ShapeInfo si;
   SolverLayout SL;
   (void)nnz_cap;
-  if (prec != MACH_F32 && prec != MACH_BF16) return 0;
+  if (prec != MACH_F32 && prec != MACH_BF16 && prec != MACH_FP8E4M3) return 0;
   if (!make_shape_info(s, &si) || si.d > 4 || !make_solver_layout(si, ranks, &SL)) return 0;
   return SL.total;
 }
@@ -547,8 +547,10 @@ mach_status mach_hooi_sweep(const void* ws_sample, uint64_t nnz_cap, const mach_
                             const int32_t* ranks, double* const* A_dev, mach_dtype prec,
                             int32_t first_mode, void* ws, size_t ws_bytes, double* fit_dev,
                             void* stream) {
-  if (prec != MACH_F32 && prec != MACH_BF16) return MACH_EUNSUPPORTED;
-  const int bf16 = prec == MACH_BF16;
+  if (prec != MACH_F32 && prec != MACH_BF16 && prec != MACH_FP8E4M3) return MACH_EUNSUPPORTED;
+  // mixed precision: bfloat16 factor entries in the sparse passes (both
+  // variants); the Gram's inputs in bfloat16 or e4m3
+  const int bf16 = prec != MACH_F32;
   Prepared P;
   mach_status rc = prepare(ws_sample, nnz_cap, s, ranks, A_dev, ws, ws_bytes, &P);
   if (rc != MACH_OK) return rc;
@@ -564,14 +566,14 @@ mach_status mach_hooi_sweep(const void* ws_sample, uint64_t nnz_cap, const mach_
     ok = ok && launch_contract_tail(P.si, P.sp, P.SL, w, ranks, density, bf16, st) == hipSuccess;
     for (int k = first_mode; k < h && ok; ++k) {
       ok = launch_form_y(P.si, P.SL, w, k, hdr, st) == hipSuccess;
-      ok = ok && launch_mode_update(P.si, P.SL, w, k, A_dev[k], hdr, st) == hipSuccess;
+      ok = ok && launch_mode_update(P.si, P.SL, w, k, A_dev[k], prec, hdr, st) == hipSuccess;
     }
     tail0 = h;
   }
   ok = ok && launch_contract_head(P.si, P.sp, P.SL, w, ranks, density, bf16, st) == hipSuccess;
   for (int k = tail0; k < d && ok; ++k) {
     ok = launch_form_y(P.si, P.SL, w, k, hdr, st) == hipSuccess;
-    ok = ok && launch_mode_update(P.si, P.SL, w, k, A_dev[k], hdr, st) == hipSuccess;
+    ok = ok && launch_mode_update(P.si, P.SL, w, k, A_dev[k], prec, hdr, st) == hipSuccess;
   }
   if (ok && fit_dev) ok = launch_fit(P.SL, w, d - 1, hdr, fit_dev, st) == hipSuccess;
   return ok ? MACH_OK : MACH_EDEVICE;

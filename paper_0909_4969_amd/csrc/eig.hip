@@ -26,10 +26,10 @@
 
 namespace mach {
 
-hipError_t launch_gram_y(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
+hipError_t launch_gram_y(const SolverLayout& SL, char* ws, int k, int prec, const SampleHdr* hdr,
                          hipStream_t st);
-hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
-                                  hipStream_t st, uint32_t* nchunk);
+hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, int prec,
+                                  const SampleHdr* hdr, hipStream_t st, uint32_t* nchunk);
 hipError_t launch_gram_xhat(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
                             char* ws, int n, hipStream_t st);
 bool sparse_tail_gram_ok(const ShapeInfo& si, const SolverLayout& SL, int n);
@@ -1948,7 +1948,7 @@ hipError_t launch_solver_init(const SolverLayout& SL, char* ws, hipStream_t st) 
 }
 
 hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k,
-                              double* A_out, const SampleHdr* hdr, hipStream_t st) {
+                              double* A_out, int prec, const SampleHdr* hdr, hipStream_t st) {
   Ctx c{&SL, ws, hdr, st};
   const ModePlan& m = SL.mp[k];
   int32_t tagval = 0x4d000000 | (k << 16) | (int32_t)m.s;
@@ -1975,7 +1975,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
   }
   if (m.s <= (uint32_t)kSmallEig) {
     uint32_t nchunk = 1;
-    hipError_t e = launch_gram_y_partials(SL, ws, k, hdr, st, &nchunk);
+    hipError_t e = launch_gram_y_partials(SL, ws, k, prec, hdr, st, &nchunk);
     if (e != hipSuccess) return e;
     SolveArgs a;
     a.part = c.d(SL.Gpart);
@@ -2073,7 +2073,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     }
     return hipGetLastError();
   }
-  hipError_t e = launch_gram_y(SL, ws, k, hdr, st);
+  hipError_t e = launch_gram_y(SL, ws, k, prec, hdr, st);
   if (e != hipSuccess) return e;
   const double* G = c.d(SL.G);
   double* V = c.d(m.Q64);

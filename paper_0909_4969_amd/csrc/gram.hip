@@ -155,20 +155,6 @@ __global__ void k_gram_reduce(const double* __restrict__ part, uint32_t nchunk, 
   G[e] = s;
 }
 
-// Picks the summation slicing; returns the number of slices.
-inline uint32_t gram_slices(GramArgs& a, size_t part_elems) {
-  uint32_t tiles = (a.X + 63) / 64;
-  uint64_t n2 = (uint64_t)a.X * a.X;
-  uint32_t nchunk = 1;
-  while (nchunk < 256 && (uint64_t)tiles * tiles * nchunk < 512 &&
-         a.Z / (2 * nchunk) >= 32 && n2 * (2 * nchunk) <= part_elems)
-    nchunk *= 2;
-  a.zchunk = (a.Z + nchunk - 1) / nchunk;
-  a.zchunk = (a.zchunk + 31) / 32 * 32;
-  nchunk = (a.Z + a.zchunk - 1) / a.zchunk;
-  return nchunk < 1 ? 1 : nchunk;
-}
-
 template <typename Load>
 hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream_t st) {
   uint32_t tiles = (a.X + 63) / 64;
@@ -599,46 +585,307 @@ hipError_t launch_gram_tail_sparse(const ShapeInfo& si, const SparsePtrs& sp, co
   return hipGetLastError();
 }
 
-// Gram partials of Y_k (dense float32 view): SL.Gpart[X][X][c], c < *nchunk.
-hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
-                                  hipStream_t st, uint32_t* nchunk) {
-  const ModePlan& m = SL.mp[k];
-  GramArgs a{};
-  a.I = m.I;
-  a.Q = m.Q;
-  a.J = m.O * m.Q;
-  a.fQ = make_fastdiv(m.Q);
-  a.kside = m.kside;
-  a.X = m.s;
-  a.Z = m.kside ? m.I : a.J;
-  a.part = (double*)(ws + SL.Gpart);
-  a.st_solver = (const int32_t*)(ws + SL.status);
-  a.hdr = hdr;
-  *nchunk = gram_slices(a, SL.Gpart_elems);
-  a.nz = *nchunk;
-  uint32_t tiles = (a.X + 63) / 64;
-  DenseLoad ld{(const float*)(ws + m.ybuf)};
-  hipLaunchKernelGGL((k_gram<DenseLoad>), dim3(tiles, tiles, *nchunk), dim3(256), 0, st, a, ld);
+// ---------------------------------------------------------------------------
+// Sweep Gram of Y_(k) on MFMA (row side Y Y^T or column side Y^T Y of the
+// float32 view (O, I_k, Q)), with the inputs in float32, bfloat16 or OCP
+// float8 e4m3:
+//   G[x][y] = sum_z M[x][z] M[y][z],  row side: M[x][z] = Y_(k)[x][z] (Z = J),
+//                                     column side: M[x][z] = Y_(k)[z][x] (Z = I).
+// Workgroup (block pair, slice) stages chunks of CW = 4096 / RB summation
+// indices of its two RB-row blocks in LDS as float32 (coalesced along
+// whichever of x, z is contiguous in Y), the next chunk's loads in flight
+// while the current one is multiplied.  Each operand is converted when read
+// from LDS:
+//   float32  v_mfma_f32_16x16x4_f32      (4 summation indices per step)
+//   bfloat16 v_mfma_f32_16x16x16_bf16    (16; round to nearest even)
+//   e4m3     v_mfma_f32_16x16x32_fp8_fp8 (32; each staged RB x CW tile is
+//            scaled by amax / 448 and rounded to nearest even, saturating)
+// Products accumulate in float32 over runs of 32 summation indices and in
+// float64 across runs (times the two tiles' scales for e4m3).  Partials go to
+// part[(x X + y) nslice + slice] for every x, y < X (both triangles).
+// ---------------------------------------------------------------------------
+struct YGramArgs {
+  const float* Y;
+  uint32_t I, Q, J;
+  FastDiv fQ;
+  int kside;
+  int xfast;               // 1: consecutive x are consecutive in Y
+  uint32_t X, Z;
+  uint32_t nb, nblk;       // row blocks, upper-triangle block pairs
+  uint32_t cps, nslice;    // chunks per slice, slices
+  double* part;
+  const SampleHdr* hdr;
+  const int32_t* st_solver;
+};
+
+// OCP float8 e4m3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits;
+// largest finite 448) of a float32, rounded to nearest even and saturated
+// at +-448; subnormals are multiples of 2^-9.
+__device__ __forceinline__ uint32_t to_e4m3(float f) {
+  const uint32_t sign = (__float_as_uint(f) >> 24) & 0x80u;
+  const float a = fabsf(f);
+  if (!(a < 448.f)) return sign | 0x7Eu;
+  if (a >= 0.015625f) {               // normal: a >= 2^-6
+    const uint32_t ua = __float_as_uint(a);
+    int e = (int)(ua >> 23) - 127;
+    const uint32_t mant = ua & 0x7FFFFFu;
+    uint32_t r = mant >> 20;
+    const uint32_t rem = mant & 0xFFFFFu;
+    if (rem > 0x80000u || (rem == 0x80000u && (r & 1u))) ++r;
+    if (r == 8u) {
+      r = 0u;
+      ++e;
+    }
+    return sign | ((uint32_t)(e + 7) << 3) | r;
+  }
+  return sign | (uint32_t)rintf(a * 512.f);   // 0..8 (8 is 2^-6, the smallest normal)
+}
+
+__device__ __forceinline__ uint32_t to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+template <int RB, int P>
+__global__ __launch_bounds__(256) void k_gram_y_mfma(YGramArgs a) {
+  if (a.hdr->status != 0 || *a.st_solver != 0) return;
+  constexpr int CW = 4096 / RB, TB = RB / 16;
+  constexpr int NT = TB * TB, TPW = NT >= 4 ? NT / 4 : 1, KSPLIT = NT >= 4 ? 1 : 4;
+  constexpr int KI = P == 0 ? 4 : P == 1 ? 16 : 32;   // summation indices per MFMA
+  constexpr int KS = CW / KI;
+  __shared__ float Ma[RB][CW + 4];
+  __shared__ float Mb[RB][CW + 4];
+  __shared__ float wmax[2][4];
+  uint32_t by = 0;
+  while ((by + 1) * (by + 2) / 2 <= blockIdx.x) ++by;
+  const uint32_t bx = blockIdx.x - by * (by + 1) / 2;
+  const bool diag = bx == by;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const uint32_t nchunk = (a.Z + CW - 1) / CW;
+  const uint32_t c0 = blockIdx.y * a.cps;
+  const uint32_t c1 = min(nchunk, c0 + a.cps);
+  // element u of this thread in a staged tile: (x, z) within the tile
+  auto xz = [&](int u, int& x, int& z) {
+    const int e = threadIdx.x + 256 * u;
+    if (a.xfast) {
+      x = e % RB;
+      z = e / RB;
+    } else {
+      z = e % CW;
+      x = e / CW;
+    }
+  };
+  auto load = [&](uint32_t row0, uint32_t zc, float* v) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      int x, z;
+      xz(u, x, z);
+      const uint32_t xg = row0 + x, zg = zc + z;
+      float val = 0.f;
+      if (xg < a.X && zg < a.Z) {
+        const uint32_t j = a.kside ? xg : zg, i = a.kside ? zg : xg;
+        const uint32_t q = a.fQ.div(j);
+        val = a.Y[(size_t)q * a.I * a.Q + (j - q * a.Q) + (size_t)i * a.Q];
+      }
+      v[u] = val;
+    }
+  };
+  v4f acc[TPW];
+  double dacc[TPW][4];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dacc[u][v] = 0.0;
+  }
+  float va[16], vb[16];
+  if (c0 < c1) {
+    load(bx * RB, c0 * CW, va);
+    if (!diag) load(by * RB, c0 * CW, vb);
+  }
+  for (uint32_t c = c0; c < c1; ++c) {
+    __syncthreads();
+    float ma = 0.f, mb = 0.f;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      int x, z;
+      xz(u, x, z);
+      Ma[x][z] = va[u];
+      ma = fmaxf(ma, fabsf(va[u]));
+      if (!diag) {
+        Mb[x][z] = vb[u];
+        mb = fmaxf(mb, fabsf(vb[u]));
+      }
+    }
+    if constexpr (P == 2) {
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1) {
+        ma = fmaxf(ma, __shfl_xor(ma, m, 64));
+        mb = fmaxf(mb, __shfl_xor(mb, m, 64));
+      }
+      if (lane == 0) {
+        wmax[0][w] = ma;
+        wmax[1][w] = mb;
+      }
+    }
+    __syncthreads();
+    if (c + 1 < c1) {
+      load(bx * RB, (c + 1) * CW, va);
+      if (!diag) load(by * RB, (c + 1) * CW, vb);
+    }
+    float sa = 1.f, sb = 1.f;
+    if constexpr (P == 2) {
+      const float amax = fmaxf(fmaxf(wmax[0][0], wmax[0][1]), fmaxf(wmax[0][2], wmax[0][3]));
+      const float bmax = diag ? amax : fmaxf(fmaxf(wmax[1][0], wmax[1][1]), fmaxf(wmax[1][2], wmax[1][3]));
+      sa = amax > 0.f ? amax / 448.f : 1.f;
+      sb = bmax > 0.f ? bmax / 448.f : 1.f;
+    }
+    const float ia = 1.f / sa, ib = 1.f / sb;
+    const double sab = (double)sa * (double)sb;
+    float (*B)[CW + 4] = diag ? Ma : Mb;
+    // float32 runs of 32 summation indices, then float64 (as for a scalar
+    // Gram: the float32 rounding of a run stays at about 32 u)
+    constexpr int FLUSH = KI >= 32 ? 1 : 32 / KI;
+    int run = 0;
+    for (int ks = (KSPLIT > 1 ? w : 0); ks < KS; ks += KSPLIT) {
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int t = (NT >= 4 ? w * TPW : 0) + u, x = t / TB, y = t % TB;
+        const float* ra = &Ma[x * 16 + li][ks * KI];
+        const float* rb = &B[y * 16 + li][ks * KI];
+        if constexpr (P == 0) {
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[lk], rb[lk], acc[u], 0, 0, 0);
+        } else if constexpr (P == 1) {
+          v4s oa, ob;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            oa[q] = (short)to_bf16(ra[4 * lk + q]);
+            ob[q] = (short)to_bf16(rb[4 * lk + q]);
+          }
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(oa, ob, acc[u], 0, 0, 0);
+        } else {
+          uint64_t oa = 0, ob = 0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            oa |= (uint64_t)to_e4m3(ra[8 * lk + q] * ia) << (8 * q);
+            ob |= (uint64_t)to_e4m3(rb[8 * lk + q] * ib) << (8 * q);
+          }
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)oa, (long)ob, acc[u], 0, 0, 0);
+        }
+      }
+      if (++run == FLUSH) {
+        run = 0;
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dacc[u][v] += (double)acc[u][v] * sab;
+          acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dacc[u][v] += (double)acc[u][v] * sab;
+      acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(&Ma[0][0]);
+  static_assert(sizeof(Ma) + sizeof(Mb) >= RB * RB * sizeof(double), "reduction buffer");
+  for (int ww = 0; ww < KSPLIT; ++ww) {
+    if (KSPLIT == 1 || w == ww) {
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int t = (NT >= 4 ? w * TPW : 0) + u, x = t / TB, y = t % TB;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double* p = red + (x * 16 + lk * 4 + v) * RB + (y * 16 + li);
+          *p = (ww == 0) ? dacc[u][v] : *p + dacc[u][v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const uint32_t sl = blockIdx.y;
+  for (int e = threadIdx.x; e < RB * RB; e += 256) {
+    const uint32_t xx = e / RB, yy = e % RB, x = bx * RB + xx, y = by * RB + yy;
+    if (x >= a.X || y >= a.X) continue;
+    a.part[((size_t)x * a.X + y) * a.nslice + sl] = red[e];
+    if (!diag) a.part[((size_t)y * a.X + x) * a.nslice + sl] = red[e];
+  }
+}
+
+template <int RB, int P>
+hipError_t gram_y_mfma_go(YGramArgs a, hipStream_t st) {
+  hipLaunchKernelGGL((k_gram_y_mfma<RB, P>), dim3(a.nblk, a.nslice), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
-// Gram of Y_k (dense float32 view) into SL.G.
-hipError_t launch_gram_y(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr,
-                         hipStream_t st) {
+template <int P>
+hipError_t gram_y_mfma_rb(const YGramArgs& a, int rb, hipStream_t st) {
+  if (rb == 16) return gram_y_mfma_go<16, P>(a, st);
+  if (rb == 32) return gram_y_mfma_go<32, P>(a, st);
+  return gram_y_mfma_go<64, P>(a, st);
+}
+
+// Sets up and launches the MFMA sweep Gram of Y_k into SL.Gpart; returns
+// the number of slices in *nslice.  prec: MACH_F32, MACH_BF16 or
+// MACH_FP8E4M3 (the Gram's input precision).
+hipError_t gram_y_mfma(const SolverLayout& SL, char* ws, int k, int prec, const SampleHdr* hdr,
+                       hipStream_t st, uint32_t* nslice) {
   const ModePlan& m = SL.mp[k];
-  GramArgs a{};
+  YGramArgs a{};
+  a.Y = (const float*)(ws + m.ybuf);
   a.I = m.I;
   a.Q = m.Q;
   a.J = m.O * m.Q;
   a.fQ = make_fastdiv(m.Q);
   a.kside = m.kside;
+  a.xfast = m.kside ? (m.Q > 1) : (m.Q == 1);
   a.X = m.s;
   a.Z = m.kside ? m.I : a.J;
   a.part = (double*)(ws + SL.Gpart);
-  a.st_solver = (const int32_t*)(ws + SL.status);
   a.hdr = hdr;
-  DenseLoad ld{(const float*)(ws + m.ybuf)};
-  return gram_run(a, ld, (double*)(ws + SL.G), SL.Gpart_elems, st);
+  a.st_solver = (const int32_t*)(ws + SL.status);
+  const int rb = a.X <= 16 ? 16 : a.X <= 32 ? 32 : 64;
+  const uint32_t cw = 4096u / (uint32_t)rb;
+  a.nb = (a.X + rb - 1) / rb;
+  a.nblk = a.nb * (a.nb + 1) / 2;
+  const uint32_t chunks = (a.Z + cw - 1) / cw;
+  // Slices of at least 4 chunks, at most 256, enough workgroups to fill
+  // the chip when there are chunks for it, and partials that fit Gpart.
+  const uint64_t n2 = (uint64_t)a.X * a.X;
+  uint32_t ns = 1;
+  while (ns < 256 && (uint64_t)a.nblk * ns < 512 && chunks >= 8u * ns && n2 * 2 * ns <= SL.Gpart_elems) ns *= 2;
+  a.cps = (chunks + ns - 1) / ns;
+  a.nslice = (chunks + a.cps - 1) / a.cps;
+  *nslice = a.nslice;
+  if (prec == MACH_BF16) return gram_y_mfma_rb<1>(a, rb, st);
+  if (prec == MACH_FP8E4M3) return gram_y_mfma_rb<2>(a, rb, st);
+  return gram_y_mfma_rb<0>(a, rb, st);
+}
+
+// Gram partials of Y_k: SL.Gpart[X][X][c], c < *nchunk.
+hipError_t launch_gram_y_partials(const SolverLayout& SL, char* ws, int k, int prec,
+                                  const SampleHdr* hdr, hipStream_t st, uint32_t* nchunk) {
+  return gram_y_mfma(SL, ws, k, prec, hdr, st, nchunk);
+}
+
+// Gram of Y_k into SL.G.
+hipError_t launch_gram_y(const SolverLayout& SL, char* ws, int k, int prec, const SampleHdr* hdr,
+                         hipStream_t st) {
+  uint32_t ns = 1;
+  hipError_t e = gram_y_mfma(SL, ws, k, prec, hdr, st, &ns);
+  if (e != hipSuccess) return e;
+  const uint32_t n2 = SL.mp[k].s * SL.mp[k].s;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((n2 + 255) / 256), dim3(256), 0, st,
+                     (const double*)(ws + SL.Gpart), ns, n2, (double*)(ws + SL.G), hdr,
+                     (const int32_t*)(ws + SL.status));
+  return hipGetLastError();
 }
 
 // Gram of the sampled unfolding Xhat_(n) (unscaled values) into SL.G.

@@ -122,8 +122,10 @@ hipError_t launch_factors_to_f32(const ShapeInfo& si, const SolverLayout& SL, ch
                                  hipStream_t st);
 
 // Gram, eigensolve and factor update of one mode from Y_k (gram.hip, eig.hip).
+// prec: input precision of the sweep Gram (MACH_F32, MACH_BF16 or
+// MACH_FP8E4M3), float32 accumulation.
 hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char* ws, int k,
-                              double* A_out, const SampleHdr* hdr, hipStream_t st);
+                              double* A_out, int prec, const SampleHdr* hdr, hipStream_t st);
 hipError_t launch_fit(const SolverLayout& SL, char* ws, int k, const SampleHdr* hdr, double* fit,
                       hipStream_t st);
 hipError_t launch_core(const ShapeInfo& si, const SolverLayout& SL, char* ws, const double* A_last,

@@ -54,7 +54,8 @@ def test_size_queries(M):
     assert sb >= 8 * cap * 2 + N // 8
     assert M.solver_workspace_bytes(shape, ranks, cap) > 0
     assert M.solver_workspace_bytes(shape, ranks, cap, M.MACH_BF16) > 0
-    assert M.solver_workspace_bytes(shape, ranks, cap, M.MACH_FP8E4M3) == 0
+    assert M.solver_workspace_bytes(shape, ranks, cap, M.MACH_FP8E4M3) > 0
+    assert M.solver_workspace_bytes(shape, ranks, cap, M.MACH_F64) == 0
     # invalid: rank above the dimension, above 16, too many modes, empty mode
     assert M.solver_workspace_bytes((8, 8, 8), (9, 2, 2), 100) == 0
     assert M.solver_workspace_bytes((64, 64, 64), (17, 2, 2), 100) == 0
