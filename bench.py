@@ -54,8 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-voxel", action="store_true",
                     help="skip the 64x64x64x256 voxel workload block")
-    ap.add_argument("--serve-requests", type=int, default=400,
-                    help="windows of the serving run (0: skip it)")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="windows of the serving run after 100 warm-up windows (0: skip it)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (the "
                          "reference kernel for scaling HBM counters; larger than the 256 MB "
@@ -147,10 +147,11 @@ def traffic_from_profiles(which):
     return d.get("bytes_per_launch", {}).get(which)
 
 
-def cpu_baseline(X, p, seed, ranks, sweeps, nnz, gpu_factors, gpu_core, gpu_fit):
+def cpu_baseline(X, p, seed, ranks, sweeps, nnz, runs):
     """The FP64 numpy oracle on the benchmarked window (window 0): coin toss,
     HOSVD, all sweeps and the core, timed in full on the host cores; then
-    the device result of the same window measured against it."""
+    the device results of the same window (one per sweep precision)
+    measured against it."""
     from threadpoolctl import threadpool_info
 
     from oracle import mach as O
@@ -181,17 +182,19 @@ def cpu_baseline(X, p, seed, ranks, sweeps, nnz, gpu_factors, gpu_core, gpu_fit)
                    f"{t3 - t2:.1f}s, core {t4 - t3:.2f}s; job {t_job:.1f}s"),
     }
     e_o, e2_o = host_measures(X, G, A)
-    e_g, e2_g = host_measures(X, gpu_core, gpu_factors)
-    acc = {
-        "window": 0, "reference": "FP64 oracle, same coins, HOSVD + same sweeps + core",
-        "sin_theta_per_mode": [round(sin_theta_host(a, b), 9) for a, b in zip(A, gpu_factors)],
-        "rel_error_e": {"gpu": e_g, "oracle": e_o, "rel_diff": abs(e_g - e_o) / e_o},
-        "rel_error_e_prime": {"gpu": e2_g, "oracle": e2_o, "rel_diff": abs(e2_g - e2_o) / e2_o},
-        "core_rel_diff": float(np.linalg.norm(gpu_core - G) / np.linalg.norm(G)),
-        "fit": {"gpu": gpu_fit, "oracle": fits[-1]},
-        "note": "e = ||X - G x_n A_n|| / ||X|| (1 - the paper's accuracy); e' = ||X - X x_n A_n A_n^T|| "
-                "/ ||X||; sin theta = sine of the largest principal angle between the subspaces",
-    }
+    acc = {"window": 0, "reference": "FP64 oracle, same coins, HOSVD + same sweeps + core",
+           "oracle": {"rel_error_e": e_o, "rel_error_e_prime": e2_o, "fit": fits[-1]}}
+    for name, r in runs.items():
+        e_g, e2_g = host_measures(X, r["core"], r["factors"])
+        acc[name] = {
+            "sin_theta_per_mode": [float(f"{sin_theta_host(a, b):.3e}") for a, b in zip(A, r["factors"])],
+            "rel_error_e": e_g, "e_over_oracle": e_g / e_o,
+            "rel_error_e_prime": e2_g,
+            "core_rel_diff": float(np.linalg.norm(r["core"] - G) / np.linalg.norm(G)),
+            "fit": r["fit"],
+        }
+    acc["note"] = ("e = ||X - G x_n A_n|| / ||X|| (1 - the paper's accuracy); e' = ||X - X x_n A_n A_n^T|| "
+                   "/ ||X||; sin theta = sine of the largest principal angle between the subspaces")
     return cb, acc
 
 
@@ -222,44 +225,61 @@ def device_windows(reqs, metrics=16, ranks=(8, 4, 16), rel_noise=0.01):
     return out
 
 
-def serving_bench(n_requests, prec_modes):
+def serving_bench(n_requests, prec_modes, warmup_windows=100, saturated_windows=400):
     """Config-5 serving: Poisson arrivals (200/s) of hosts x 16 x T windows
     from 8 streams (hosts in {32, 64, 128} per stream, T uniform in
     [1024, 16384]), p = 0.05, ranks (8, 4, 16); a stream's first window runs
     HOSVD + 6 sweeps, later windows the warm time-mode update + 3 sweeps.
-    Continuous batching (8 windows in flight over 4 HIP streams) against
-    plain per-request solves (one window at a time)."""
+    Continuous batching (8 windows in flight over 8 HIP streams) against
+    plain per-request solves (one window at a time).  Latency figures skip
+    the first `warmup_windows` windows.  The saturated run queues
+    `saturated_windows` windows at once (the device is never idle), so its
+    rate is the throughput each mode can sustain."""
     import numpy as np
     import torch
 
     import synth
     from paper_0909_4969_amd import mach as M
     from paper_0909_4969_amd.serve import Engine, ServeConfig, latency_summary
-    reqs = synth.serving_stream(n_requests=n_requests)
+    reqs = synth.serving_stream(n_requests=n_requests + warmup_windows)
     wins = device_windows(reqs)
     torch.cuda.synchronize()
-    out = {"workload": f"poisson-200/s {n_requests} windows, 8 streams, hosts x 16 x T, "
-                       f"T in [1024,16384], p=0.05, ranks (8,4,16)",
+    out = {"workload": f"poisson-200/s {n_requests} windows after {warmup_windows} warm-up, 8 streams, "
+                       f"hosts x 16 x T, T in [1024,16384], p=0.05, ranks (8,4,16)",
            "windows_resident_in_hbm": True}
-    modes = [("continuous_f32", dict(max_active=8, hip_streams=4), M.MACH_F32),
+    modes = [("continuous_f32", dict(max_active=8, hip_streams=8), M.MACH_F32),
              ("per_request_f32", dict(max_active=1, hip_streams=1), M.MACH_F32)]
-    modes += [(f"continuous_{name}", dict(max_active=8, hip_streams=4), code) for name, code in prec_modes]
+    modes += [(f"continuous_{name}", dict(max_active=8, hip_streams=8), code) for name, code in prec_modes]
+
+    def work(cfg, res):
+        return sum(r.nnz * ((cfg.sweeps_warm + 1.0 / 3.0) if r.warm else cfg.sweeps_cold) for r in res)
+
     for name, kw, prec in modes:
         cfg = ServeConfig(ranks=(8, 4, 16), p=0.05, sweeps_cold=6, sweeps_warm=3, prec=prec,
                           hbm_budget=64 << 30, **kw)
         eng = Engine(cfg)
-        eng.run(wins[:8], realtime=False)            # warm-up: kernels, allocator
+        eng.run(wins[:8], realtime=False)            # kernels, allocator
         eng.resident.clear()
         torch.cuda.synchronize()
         res = eng.run(wins, realtime=True)
-        summ = latency_summary(res)
-        work = sum(r.nnz * ((cfg.sweeps_warm + 1.0 / 3.0) if r.warm else cfg.sweeps_cold) for r in res)
-        summ["nnz_per_s"] = work / summ["span_s"]
-        summ["mean_fit"] = float(np.mean([r.fit for r in res]))
-        summ["warm_windows"] = sum(1 for r in res if r.warm)
-        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
-        del eng, res
+        kept = [r for r in res if r.req_id >= warmup_windows]
+        summ = latency_summary(kept)
+        summ["nnz_per_s"] = work(cfg, kept) / summ["span_s"]
+        summ["mean_fit"] = float(np.mean([r.fit for r in kept]))
+        summ["warm_windows"] = sum(1 for r in kept if r.warm)
+        # saturated: every window queued at time 0
+        eng.resident.clear()
         torch.cuda.synchronize()
+        sat = eng.run(wins[:saturated_windows], realtime=False)
+        span = max(r.done_s for r in sat) - min(r.admit_s for r in sat)
+        summ["saturated"] = {"windows": len(sat), "span_s": round(span, 4),
+                             "windows_per_s": round(len(sat) / span, 1),
+                             "nnz_per_s": round(work(cfg, sat) / span, 1)}
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+        del eng, res, sat
+        torch.cuda.synchronize()
+    out["note"] = ("continuous: up to 8 windows in flight on 8 HIP streams, each window's kernels on its "
+                   "own stream; per_request: one window at a time; mixed modes as in `precision`")
     return out
 
 
@@ -475,43 +495,32 @@ def main():
                            "input_GBs_tick_coins": round(X.numel() * 4 / (coin_ms["ticks"] / 1e3) / 1e9, 1),
                            "note": "coin toss + compaction + layouts of the window; tick coins "
                                    "keyed on (seed, series, absolute tick)"}
-    # Mixed precision on the same window: sweeps after HOSVD with bfloat16
-    # factor entries in the sparse TTM, against the float32 run of the last
-    # per-phase window.
-    A32 = [a.clone() for a in dec.factors]
-    fit32 = float(dec.fit.item())
-    last_win = 1000 + PHASE_WINDOWS - 1
-    dec.sample(X, args.seed, last_win)
-    dec.hosvd()
-    torch.cuda.synchronize()
-    eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    eb0.record()
-    for _ in range(sweeps):
-        dec.sweep(prec=M.MACH_BF16)
-    eb1.record()
-    torch.cuda.synchronize()
-    if dec.status()[0] != 0:
-        raise SystemExit("device status after the bfloat16 sweeps")
-    sin_max = max(sin_theta_host(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(A32, dec.factors))
+    # The benchmarked window once more (window 0: HOSVD + sweeps + core) in
+    # each sweep precision, for the precision comparison and the accuracy
+    # against the oracle in the CPU leg.
+    runs = {}
+    for name, code in (("f32", M.MACH_F32), ("bf16", M.MACH_BF16), ("fp8", M.MACH_FP8E4M3)):
+        dec.sample(X, args.seed, 0)
+        dec.hosvd()
+        torch.cuda.synchronize()
+        eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        eb0.record()
+        for _ in range(sweeps):
+            dec.sweep(prec=code)
+        eb1.record()
+        dec.core()
+        if dec.status()[0] != 0:
+            raise SystemExit(f"device status of the {name} window")
+        runs[name] = {"sweep_ms": eb0.elapsed_time(eb1) / sweeps,
+                      "factors": [a.cpu().numpy() for a in dec.factors],
+                      "core": dec.G.cpu().numpy(), "fit": float(dec.fit.item())}
     out["precision"] = {
-        "window": last_win,
-        "f32": {"sweep_ms": round(r["per"]["sweeps_ms"][-1] / sweeps, 4), "fit": fit32},
-        "bf16": {"sweep_ms": round(eb0.elapsed_time(eb1) / sweeps, 4), "fit": float(dec.fit.item()),
-                 "max_sin_theta_vs_f32": sin_max},
-        "note": "bf16 = sparse-TTM factor entries rounded to bfloat16, float32 sums, float64 eigensolve",
+        "window": 0,
+        **{k: {"sweep_ms": round(v["sweep_ms"], 4), "fit": v["fit"]} for k, v in runs.items()},
+        "note": "f32: float32 factor entries and Gram inputs; bf16: factor entries of the sparse passes "
+                "and Gram inputs in bfloat16; fp8: factor entries in bfloat16, Gram inputs in OCP e4m3 "
+                "scaled per tile; float32 accumulation and float64 eigensolve in all three",
     }
-    # The benchmarked window once more (window 0: HOSVD + sweeps + core) for
-    # the accuracy comparison with the oracle in the CPU leg.
-    dec.sample(X, args.seed, 0)
-    dec.hosvd()
-    for _ in range(sweeps):
-        dec.sweep()
-    dec.core()
-    if dec.status()[0] != 0:
-        raise SystemExit("device status of the accuracy window")
-    gpu_factors = [a.cpu().numpy() for a in dec.factors]
-    gpu_core = dec.G.cpu().numpy()
-    gpu_fit = float(dec.fit.item())
     del dec
     torch.cuda.synchronize()
 
@@ -525,9 +534,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if args.serve_requests > 0:
-        out["serving"] = serving_bench(args.serve_requests, [("bf16", M.MACH_BF16)])
+        out["serving"] = serving_bench(args.serve_requests, [("bf16", M.MACH_BF16),
+                                                             ("fp8", M.MACH_FP8E4M3)])
     if not args.no_cpu_baseline:
-        cb, acc = cpu_baseline(X_np, p, args.seed, ranks, sweeps, nnz, gpu_factors, gpu_core, gpu_fit)
+        cb, acc = cpu_baseline(X_np, p, args.seed, ranks, sweeps, nnz, runs)
         out["cpu_baseline"] = cb
         out["accuracy"] = acc
     print(json.dumps(out), flush=True)
