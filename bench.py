@@ -63,6 +63,14 @@ def parse():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the TTM traffic summary from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this script with --copy-mib, and exit")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="write the kernel-time summary (profiles/) from a rocprofv3 --kernel-trace "
+                         "--stats run of this script, and exit")
+    ap.add_argument("--pmc-mfma", metavar="DIR",
+                    help="write the MFMA utilisation summary of the Gram kernels from a rocprofv3 "
+                         "--pmc run (SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE "
+                         "SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_INSTS_VALU_MFMA_MOPS_BF16 "
+                         "SQ_INSTS_VALU_MFMA_MOPS_F64) of this script, and exit")
     return ap.parse_args()
 
 
@@ -119,12 +127,158 @@ def pmc_summary(fetch_dir, write_dir, copy_mib):
            "bytes_per_launch": {k: int(fetch[k] * 1024 * f_scale + write[k] * 1024 * w_scale)
                                 for k in ("ttm_head_rows", "ttm_tail_cols")},
            "commands": [
-               "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE "
+               "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE "
                f"--output-format csv -d $R/{fd} -o run -- python3 $R/bench.py --steps 1 "
                f"--warmup 1 --no-cpu-baseline --serve-requests 0 --copy-mib {copy_mib}",
                f"(the same with --pmc WRITE_SIZE and -d $R/{wd})",
                f"python3 bench.py --pmc-summary {fd} {wd} --copy-mib {copy_mib}"]}
     return out
+
+
+MFMA_JSON = os.path.join(ROOT, "profiles", "mfma_util_gram_kernels.json")
+
+
+def source_digest(name):
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_0909_4969_amd", "csrc", name), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def mfma_summary(d):
+    """Per-kernel MFMA figures of the Gram (and eigensolve) kernels from a
+    counter CSV: utilisation = SQ_VALU_MFMA_BUSY_CYCLES (summed over SIMDs) /
+    (device busy cycles x SIMDs), and the MFMA flops counted by
+    SQ_INSTS_VALU_MFMA_MOPS_* (units of 512 flops), averaged over the
+    dispatches of each kernel."""
+    import csv
+    import glob
+    import re
+    path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+    per = {}
+    for r in csv.DictReader(open(path)):
+        n = r["Kernel_Name"]
+        m = re.search(r"(k_gram_y_mfma<\d+, \d>|k_gram_mfma<\d+, \w+>|k_mode_ss<\d+>|"
+                      r"k_mode_solve<\d+, \d+>)", n)
+        if not m:
+            continue
+        key = (m.group(1), r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+        per.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    acc = {}
+    for (k, _), c in per.items():
+        acc.setdefault(k, []).append(c)
+    # GRBM_GUI_ACTIVE arrives summed over the XCDs: busy cycles of the
+    # device = that sum / XCDs; SQ_VALU_MFMA_BUSY_CYCLES is summed over SIMDs.
+    agent = [r for r in csv.DictReader(open(glob.glob(os.path.join(d, "**", "*agent_info.csv"),
+                                                       recursive=True)[0])) if r["Agent_Type"] == "GPU"][0]
+    nxcc, simds = int(agent["Num_Xcc"]), int(agent["Simd_Count"])
+    out = {}
+    for k, lst in sorted(acc.items()):
+        def avg(name):
+            return sum(x.get(name, 0.0) for x in lst) / len(lst)
+        busy, gui = avg("SQ_VALU_MFMA_BUSY_CYCLES"), avg("GRBM_GUI_ACTIVE") / nxcc
+        flops = 512.0 * (avg("SQ_INSTS_VALU_MFMA_MOPS_F32") + avg("SQ_INSTS_VALU_MFMA_MOPS_BF16") +
+                         avg("SQ_INSTS_VALU_MFMA_MOPS_F64"))
+        out[k] = {"dispatches": len(lst), "mfma_busy_cycles": busy, "gui_active_cycles": gui,
+                  "mfma_util": round(busy / (gui * simds), 5) if gui else None,
+                  "mfma_flops_per_dispatch": flops}
+    rd = os.path.relpath(d, ROOT)
+    return {"gram_source_digest": source_digest("gram.hip"), "kernels": out,
+            "commands": ["cd /tmp && export TMPDIR=/tmp && timeout -s KILL 300 rocprofv3 --pmc "
+                         "SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE SQ_INSTS_VALU_MFMA_MOPS_F32 "
+                         "SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_INSTS_VALU_MFMA_MOPS_F64 --output-format csv "
+                         f"-d $R/{rd} -o run -- python3 $R/bench.py --steps 1 --warmup 1 --no-cpu-baseline "
+                         "--serve-requests 0",
+                         f"python3 bench.py --pmc-mfma {rd}"]}
+
+
+TRACE_MD = os.path.join(ROOT, "profiles", "kernels_monitoring-128x16x16384_voxel-64x64x64x256.md")
+
+
+def trace_summary(d):
+    """Markdown summary of a kernel trace of this script: the top kernels by
+    total time, and the sparse passes split into cold launches (the first
+    one after each 1 GiB cache flush) and warm ones."""
+    import csv
+    import glob
+    import re
+    rows = list(csv.DictReader(open(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)[0])))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+
+    def short(n):
+        n = n.replace("mach::(anonymous namespace)::", "").replace("mach::", "")
+        return re.sub(r"\(.*$", "", n)
+    tot = {}
+    for r in rows:
+        k = short(r["Kernel_Name"])
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        t = tot.setdefault(k, [0, 0.0, 1e30])
+        t[0] += 1
+        t[1] += dt
+        t[2] = min(t[2], dt)
+    # cold / warm split of the sparse passes (float32 variants); the tiled
+    # head-row pass is its tile kernel plus the partial sum that follows
+    passes = {"ttm_head_rows": [], "ttm_tail_cols": [], "voxel_head_rows": [], "voxel_tail_cols": []}
+    flushed = False
+    for i, r in enumerate(rows):
+        n = r["Kernel_Name"]
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        if "FillFunctor<float>" in n and int(r["Grid_Size_X"]) >= (1 << 26):
+            flushed = True
+            continue
+        key = None
+        if "k_rows_tiled<16, 0>" in n:
+            nxt = rows[i + 1] if i + 1 < len(rows) else None
+            if nxt is not None and "k_rows_tiled_sum" in nxt["Kernel_Name"]:
+                dt = (int(nxt["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            key = "ttm_head_rows"
+        elif "k_spc<2, 8, 4, 1, 0, 1>" in n:
+            key = "ttm_tail_cols"
+        elif "k_spc<2, 16, 12, 0, 0, 0>" in n:
+            key = "voxel_head_rows"
+        elif "k_spc<2, 16, 12, 1, 0, 1>" in n:
+            key = "voxel_tail_cols"
+        if key:
+            passes[key].append((flushed, dt))
+            if key.endswith("tail_cols"):
+                flushed = False
+    total = sum(v[1] for v in tot.values())
+    rd = os.path.relpath(d, ROOT)
+    lines = ["# Kernel time of the benchmark run (monitoring window 128 x 16 x 16384 and voxel "
+             "workload 64 x 64 x 64 x 256)", "",
+             "Command (GPU box, repository root as `$R`):", "",
+             "    cd /tmp && export TMPDIR=/tmp && timeout -k 10 300 rocprofv3 --kernel-trace --stats \\",
+             f"      --output-format csv -d $R/{rd} -o run -- \\",
+             "      python3 $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline --serve-requests 0",
+             f"    python3 bench.py --trace-summary {rd}", "",
+             "Sparse passes (float32; the tiled head-row pass is its tile kernel through the end of its "
+             "partial-sum kernel). Cold = the first pass of its kind after a 1 GiB buffer write "
+             "(the cache flush of the bench's cold timing); warm = every other launch.", "",
+             "| pass | cold launches | cold avg us | warm launches | warm avg us |", "|---|---:|---:|---:|---:|"]
+    for k, v in passes.items():
+        c = [dt for f, dt in v if f]
+        w = [dt for f, dt in v if not f]
+        if v:
+            lines.append(f"| {k} | {len(c)} | {sum(c) / max(1, len(c)):.2f} | {len(w)} | "
+                         f"{sum(w) / max(1, len(w)):.2f} |")
+    lines += ["", f"Top kernels by total time (all kernels: {total / 1e3:.2f} ms):", "",
+              "| kernel | calls | total ms | avg us | min us |", "|---|---:|---:|---:|---:|"]
+    for k, (n, t, mn) in sorted(tot.items(), key=lambda kv: -kv[1][1])[:30]:
+        lines.append(f"| {k} | {n} | {t / 1e3:.3f} | {t / n:.2f} | {mn:.2f} |")
+    return "\n".join(lines) + "\n"
+
+
+def mfma_from_profiles():
+    """The committed MFMA summary if it was taken on the current Gram source."""
+    try:
+        with open(MFMA_JSON) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("gram_source_digest") != source_digest("gram.hip"):
+        return None
+    return {k: {"mfma_util": v["mfma_util"], "mfma_flops_per_dispatch": v["mfma_flops_per_dispatch"]}
+            for k, v in d["kernels"].items() if k.startswith("k_gram")}
 
 
 def kernel_source_digest():
@@ -433,6 +587,18 @@ def sin_theta_host(A_ref, A):
 
 def main():
     args = parse()
+    if args.trace_summary:
+        md = trace_summary(args.trace_summary)
+        with open(TRACE_MD, "w") as f:
+            f.write(md)
+        print(md)
+        return
+    if args.pmc_mfma:
+        d = mfma_summary(args.pmc_mfma)
+        with open(MFMA_JSON, "w") as f:
+            json.dump(d, f, indent=1)
+        print(json.dumps(d))
+        return
     if args.pmc_summary:
         d = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_mib or 256)
         with open(TRAFFIC_JSON, "w") as f:
@@ -473,6 +639,7 @@ def main():
         "phases_windows": PHASE_WINDOWS,
         "sweep_only_nnz_per_s": round(nnz / (r["phase"]["sweep_ms"] / 1e3), 1),
         "roofline": pass_roofline(shape, ranks, nnz, h, r),
+        "mfma": mfma_from_profiles(),
     }
     # The coin toss + layouts with stream (tick-keyed) coins against window
     # coins on the same window, 10 calls each (not part of the timed region).
