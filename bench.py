@@ -657,11 +657,35 @@ def main():
         coin_ms[kind] = ev2[0].elapsed_time(ev2[1]) / 10
     if dec.status()[0] != 0:
         raise SystemExit("device status after the coin comparison")
+    # A window slid by `hop` ticks along its stream: the toss of the new
+    # window from the previous window's sample against a fresh toss.
+    hop = shape[2] // 8
+    Xs = torch.cat([X, X[..., :hop]], dim=2)
+    Xa, Xb = Xs[..., :shape[2]].contiguous(), Xs[..., hop:].contiguous()
+    del Xs
+    prev = M.sample(Xa, p, args.seed, 0, cap=dec.cap, tick0=100000)
+    slid = M.SampleWorkspace(shape, dec.cap, torch.empty_like(dec.sw.buf))
+    for kind in ("slide", "fresh"):
+        ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev2[0].record()
+        for i in range(10):
+            M.sample(Xb, p, args.seed, 0, ws=slid, tick0=100000 + hop,
+                     prev=prev if kind == "slide" else None)
+        ev2[1].record()
+        torch.cuda.synchronize()
+        coin_ms[kind] = ev2[0].elapsed_time(ev2[1]) / 10
+    if slid.status()[0] != 0:
+        raise SystemExit("device status after the slide comparison")
+    del prev, slid, Xa, Xb
     out["stream_coins"] = {"sample_ms_window_coins": round(coin_ms["window"], 4),
                            "sample_ms_tick_coins": round(coin_ms["ticks"], 4),
                            "input_GBs_tick_coins": round(X.numel() * 4 / (coin_ms["ticks"] / 1e3) / 1e9, 1),
+                           "slide_hop_ticks": hop,
+                           "sample_ms_slid_window": round(coin_ms["slide"], 4),
+                           "sample_ms_same_window_fresh": round(coin_ms["fresh"], 4),
                            "note": "coin toss + compaction + layouts of the window; tick coins "
-                                   "keyed on (seed, series, absolute tick)"}
+                                   "keyed on (seed, series, absolute tick); the slid window reuses the "
+                                   "previous window's coins and kept values for the shared ticks"}
     # The benchmarked window once more (window 0: HOSVD + sweeps + core) in
     # each sweep precision, for the precision comparison and the accuracy
     # against the oracle in the CPU leg.

@@ -119,6 +119,27 @@ mach_status mach_sample_ticks(const mach_shape* s, mach_dtype x_dtype, const voi
                               uint64_t seed, uint64_t tick0, void* ws, size_t ws_bytes,
                               uint64_t nnz_cap, void* stream);
 
+/* The tick-keyed toss of a window that slides along a stream (Remark 2: the
+ * coin of a measurement is tossed once, when it arrives), reusing an
+ * earlier window's sample.  ws_prev holds a completed mach_sample_ticks (or
+ * mach_sample_ticks_slide) of a window of the same shape s, the same seed,
+ * p and nnz_cap, at its own first tick tick0p (read on the device).  Every
+ * measurement (j, tau) of the new window that lies in the earlier window
+ * takes its coin and its kept value (float32 input) from ws_prev: no
+ * Philox block and no read of X_dev for it; the others are tossed as in
+ * mach_sample_ticks and their values read from X_dev.  For float64 input
+ * only the coins are reused (the sum of squares needs the float64 values).
+ * The result - mask, kept list, layouts, sum of squares, kept count - is
+ * bit for bit that of mach_sample_ticks on the new window, provided X_dev
+ * holds, in the overlap, the values the earlier window was sampled from.
+ * If ws_prev is not a valid tick-keyed sample with the same seed, p and
+ * capacity (its header is checked on the device), every measurement is
+ * tossed afresh, with the same result.  ws_prev is read only and must not
+ * be ws; arguments and errors otherwise as for mach_sample_ticks. */
+mach_status mach_sample_ticks_slide(const mach_shape* s, mach_dtype x_dtype, const void* X_dev,
+                                    double p, uint64_t seed, uint64_t tick0, const void* ws_prev,
+                                    void* ws, size_t ws_bytes, uint64_t nnz_cap, void* stream);
+
 /* Bytes of the solver workspace for shape s and ranks R_1..R_d (host array
  * of d int32).  prec is the precision mach_hooi_sweep will be called with
  * (MACH_F32, MACH_BF16 or MACH_FP8E4M3; the workspace serves all three).

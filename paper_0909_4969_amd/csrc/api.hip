@@ -171,6 +171,23 @@ mach_status mach_sample_ticks(const mach_shape* s, mach_dtype x_dtype, const voi
   return e == hipSuccess ? MACH_OK : MACH_EDEVICE;
 }
 
+mach_status mach_sample_ticks_slide(const mach_shape* s, mach_dtype x_dtype, const void* X_dev,
+                                    double p, uint64_t seed, uint64_t tick0, const void* ws_prev,
+                                    void* ws, size_t ws_bytes, uint64_t nnz_cap, void* stream) {
+  ShapeInfo si;
+  if (!make_shape_info(s, &si)) return MACH_EINVAL;
+  if (x_dtype != MACH_F64 && x_dtype != MACH_F32) return MACH_EUNSUPPORTED;
+  if (!X_dev || !ws || !ws_prev || ws_prev == ws || !(p > 0.0 && p <= 1.0)) return MACH_EINVAL;
+  if (((uintptr_t)X_dev & 15) || ((uintptr_t)ws & 255) || ((uintptr_t)ws_prev & 255)) return MACH_EINVAL;
+  if (nnz_cap < 1 || nnz_cap > (1ull << 31)) return MACH_EINVAL;
+  if (tick0 > ~0ull - si.dims[si.d - 1]) return MACH_EINVAL;
+  SampleLayout L = sample_layout(si, nnz_cap);
+  if (ws_bytes < L.total) return MACH_ENOMEM;
+  hipError_t e = launch_sample_slide(si, x_dtype == MACH_F64, X_dev, p, seed, tick0, (char*)ws, L, nnz_cap,
+                                     (const char*)ws_prev, (hipStream_t)stream);
+  return e == hipSuccess ? MACH_OK : MACH_EDEVICE;
+}
+
 mach_status mach_read_status(const void* ws_sample, const void* ws_solver, void* stream,
                              int32_t* status_out, uint64_t* nnz_out, double* sumsq_out) {
   if (!ws_sample) return MACH_EINVAL;

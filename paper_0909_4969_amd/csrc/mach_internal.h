@@ -115,5 +115,11 @@ __device__ __forceinline__ uint32_t bit_rank(const uint64_t* bitmap, const uint3
 hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, double p,
                          uint64_t seed, uint64_t window, char* ws, const SampleLayout& L,
                          uint64_t cap, hipStream_t st, int coin = 0);
+// Tick-keyed toss of a window from an earlier window's sample (same layout).
+hipError_t launch_sample_slide(const ShapeInfo& si, int x_is_f64, const void* X, double p,
+                               uint64_t seed, uint64_t tick0, char* ws, const SampleLayout& L,
+                               uint64_t cap, const char* ws_prev, hipStream_t st);
+// Kept count, status and the CSR / CSC layouts of a tossed sample.
+hipError_t launch_layouts(const ShapeInfo& si, char* ws, const SampleLayout& L, hipStream_t st);
 
 }  // namespace mach

@@ -174,6 +174,100 @@ __global__ __launch_bounds__(kThreads) void k_sample_mask_ticks(uint32_t N, Fast
   if (threadIdx.x == 0) blkcnt[blockIdx.x] = tot;
 }
 
+// ---------------------------------------------------------------------------
+// Sliding window of a stream (Remark 2: a coin per measurement as it
+// arrives): the window of ticks tick0 .. tick0 + T - 1 built from the sample
+// of an earlier window of the same series (ticks tick0p .. tick0p + T - 1,
+// same seed, keep threshold and capacity).  A measurement (j, tau) inside
+// the earlier window keeps that window's coin and kept value (its bit and
+// its entry are copied, no Philox block and no read of X); a measurement
+// outside it is tossed as in k_sample_mask_ticks and its value read from X.
+// Coins are keyed on (seed, j, tau) either way, so the result equals a fresh
+// toss of the whole window bit for bit.  If the earlier sample is not a
+// valid tick-keyed sample with the same seed, threshold and capacity, every
+// measurement is tossed afresh.
+// ---------------------------------------------------------------------------
+struct PrevSample {
+  const SampleHdr* hdr;
+  const uint64_t* bitmap;
+  const uint32_t* wrank;
+  const Entry* coo;
+};
+
+// Kept entries with linear index below l (reads no bitmap word past the
+// last one when l is a multiple of 64).
+__device__ __forceinline__ uint32_t rank_at(const uint64_t* bitmap, const uint32_t* wrank, uint32_t l) {
+  return (l & 63u) ? bit_rank(bitmap, wrank, l) : wrank[l >> 6];
+}
+
+__device__ __forceinline__ bool prev_usable(const PrevSample& pv, uint64_t seed, uint64_t thresh,
+                                            uint64_t cap) {
+  const SampleHdr* h = pv.hdr;
+  return h->magic == kSampleMagic && h->coin == 1 && h->seed == seed && h->thresh == thresh &&
+         h->cap == cap && h->status == 0 && h->nnz <= cap;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sample_mask_slide(uint32_t N, FastDiv fT, uint64_t thresh,
+                                                                uint64_t seed, uint64_t tick0,
+                                                                uint64_t cap, PrevSample pv,
+                                                                uint64_t* __restrict__ bitmap,
+                                                                uint32_t* __restrict__ blkcnt) {
+  __shared__ uint32_t sh[4];
+  const uint32_t s_lo = (uint32_t)seed, s_hi = (uint32_t)(seed >> 32);
+  const bool reuse = prev_usable(pv, seed, thresh, cap);
+  const uint64_t tick0p = pv.hdr->window;
+  const uint32_t w = blockIdx.x * kSampleBlockWords + threadIdx.x;
+  uint64_t bits = 0;
+  const uint32_t l0 = w * 64u;
+  if (l0 < N) {
+    uint32_t j = fT.div(l0), t = l0 - j * fT.d;
+    uint64_t tau = tick0 + t;
+    uint32_t c[4] = {0u, 0u, 0u, 0u};
+    uint64_t cq = ~0ull;
+    uint32_t cj = ~0u;
+    uint32_t pw = ~0u;
+    uint64_t pword = 0;
+    const uint32_t nb = min(64u, N - l0);
+    for (uint32_t b = 0; b < nb; ++b) {
+      const uint64_t tp = tau - tick0p;      // position in the earlier window (wraps if before it)
+      uint64_t keep;
+      if (reuse && tp < fT.d) {
+        const uint32_t lp = j * fT.d + (uint32_t)tp;
+        if ((lp >> 6) != pw) {
+          pw = lp >> 6;
+          pword = pv.bitmap[pw];
+        }
+        keep = (pword >> (lp & 63u)) & 1ull;
+      } else {
+        const uint64_t q = tau >> 2;
+        if (q != cq || j != cj) {
+          c[0] = (uint32_t)q;
+          c[1] = (uint32_t)(q >> 32);
+          c[2] = j;
+          c[3] = 0u;
+          philox4x32_10(c, s_lo, s_hi);
+          cq = q;
+          cj = j;
+        }
+        const uint32_t sel = (uint32_t)tau & 3u;
+        const uint32_t word = sel == 0 ? c[0] : sel == 1 ? c[1] : sel == 2 ? c[2] : c[3];
+        keep = (uint64_t)word < thresh;
+      }
+      bits |= keep << b;
+      if (++t == fT.d) {
+        t = 0;
+        ++j;
+        tau = tick0;
+      } else {
+        ++tau;
+      }
+    }
+  }
+  bitmap[w] = bits;
+  uint32_t tot = block_sum256<uint32_t>((uint32_t)__popcll(bits), sh);
+  if (threadIdx.x == 0) blkcnt[blockIdx.x] = tot;
+}
+
 // Single-workgroup exclusive scan in place over a[0..n); a[n] receives the total.
 __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, uint32_t n) {
   __shared__ uint32_t part[1024];
@@ -318,6 +412,117 @@ __global__ __launch_bounds__(kThreads) void k_sample_compact(const XT* __restric
   if (threadIdx.x == 0) sumsq_part[b] = s;
 }
 
+// Word ranks of a block (as the prologue of k_sample_compact).
+__global__ __launch_bounds__(kThreads) void k_word_ranks(const uint64_t* __restrict__ bitmap,
+                                                         const uint32_t* __restrict__ blkoff,
+                                                         uint32_t* __restrict__ wrank) {
+  __shared__ uint32_t sh[4];
+  const uint32_t w = blockIdx.x * kSampleBlockWords + threadIdx.x;
+  uint32_t tot;
+  const uint32_t ex = block_exscan256((uint32_t)__popcll(bitmap[w]), sh, &tot);
+  wrank[w] = blkoff[blockIdx.x] + ex;
+}
+
+// The shared measurements of a slid window, one wave per series j: in both
+// windows they are one run of the l-ordered kept list (ticks a .. b - 1 of
+// the new window, a + shift .. b + shift - 1 of the earlier one, shift =
+// tick0 - tick0p), so the run is copied with its linear indices moved by
+// -shift.  Nothing is copied when the earlier sample is not usable.
+__global__ __launch_bounds__(256) void k_slide_copy_runs(uint32_t nseries, uint32_t T, uint64_t tick0,
+                                                         uint64_t seed, uint64_t thresh, uint64_t cap,
+                                                         PrevSample pv,
+                                                         const uint64_t* __restrict__ bitmap,
+                                                         const uint32_t* __restrict__ wrank,
+                                                         const uint32_t* __restrict__ total,
+                                                         Entry* __restrict__ coo) {
+  if (!prev_usable(pv, seed, thresh, cap)) return;
+  const uint32_t j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= nseries) return;
+  const uint64_t tick0p = pv.hdr->window;
+  // overlap in new-window ticks [a, b)
+  const int64_t shift = (int64_t)(tick0 - tick0p);   // ticks wrap to a signed difference
+  const int64_t a64 = shift < 0 ? -shift : 0, b64 = shift < 0 ? (int64_t)T : (int64_t)T - shift;
+  if (a64 >= b64 || a64 >= (int64_t)T) return;
+  const uint32_t a = (uint32_t)a64, b = (uint32_t)b64;
+  // ranks in the new window (its word ranks are written, its total is the
+  // scan's last entry: wrank past the last word is not written yet)
+  const uint32_t N = nseries * T;
+  const uint32_t dst0 = rank_at(bitmap, wrank, j * T + a);
+  const uint32_t dst1 = j * T + b == N ? *total : rank_at(bitmap, wrank, j * T + b);
+  const uint32_t src0 = rank_at(pv.bitmap, pv.wrank, (uint32_t)((int64_t)(j * T + a) + shift));
+  const uint32_t n = dst1 - dst0;
+  for (uint32_t k = lane; k < n; k += 64) {
+    Entry e = pv.coo[src0 + k];
+    e.l = (uint32_t)((int64_t)e.l - shift);
+    if (dst0 + k < cap) coo[dst0 + k] = e;
+  }
+}
+
+// Compaction of a slid window: as k_sample_compact (same elements per
+// thread, same order, so the same sum of squares), the values of the shared
+// measurements read back from the kept list where k_slide_copy_runs put
+// them, the others from X and written.
+template <typename XT>
+__global__ __launch_bounds__(kThreads) void k_sample_compact_slide(const XT* __restrict__ X, uint32_t N,
+                                                                   FastDiv fT, uint64_t tick0,
+                                                                   uint64_t seed, uint64_t thresh,
+                                                                   PrevSample pv,
+                                                                   const uint64_t* __restrict__ bitmap,
+                                                                   const uint32_t* __restrict__ blkoff,
+                                                                   const uint32_t* __restrict__ wrank,
+                                                                   Entry* __restrict__ coo, uint64_t cap,
+                                                                   double* __restrict__ sumsq_part) {
+  __shared__ uint64_t words[kSampleBlockWords];
+  __shared__ uint32_t lrank[kSampleBlockWords];
+  __shared__ double shd[4];
+  // float64 input: the sum of squares needs the float64 value, which the
+  // earlier sample does not hold, so only its coins are reused
+  const bool reuse = sizeof(XT) == 4 && prev_usable(pv, seed, thresh, cap);
+  const uint64_t tick0p = pv.hdr->window;
+  const uint32_t b = blockIdx.x;
+  const uint32_t base_word = b * kSampleBlockWords;
+  const uint32_t off = blkoff[b];
+  words[threadIdx.x] = bitmap[base_word + threadIdx.x];
+  lrank[threadIdx.x] = wrank[base_word + threadIdx.x] - off;
+  __syncthreads();
+  double ss = 0.0;
+  const uint32_t base_elem = b * kSampleBlockElems;
+  for (int it = 0; it < 16; ++it) {
+    uint32_t g = it * kThreads + threadIdx.x;
+    uint32_t e0 = base_elem + 4u * g;
+    uint32_t wi = g >> 4, sh4 = (g & 15u) * 4u;
+    uint64_t word = words[wi];
+    uint32_t nib = (uint32_t)(word >> sh4) & 15u;
+    if (nib == 0) continue;
+    uint64_t below = sh4 ? (word & ((~0ull) >> (64 - sh4))) : 0ull;
+    uint64_t r = (uint64_t)off + lrank[wi] + (uint32_t)__popcll(below);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if ((nib >> k) & 1u) {
+        const uint32_t l = e0 + k;
+        const uint64_t tp = tick0 + fT.mod(l) - tick0p;   // tick in the earlier window
+        double xv;
+        if (reuse && tp < fT.d) {
+          xv = (double)(r < cap ? coo[r].v : 0.f);
+        } else {
+          const XT x = X[l];
+          xv = (double)x;
+          if (r < cap) {
+            Entry en;
+            en.l = l;
+            en.v = (float)x;
+            coo[r] = en;
+          }
+        }
+        ss += xv * xv;
+        ++r;
+      }
+    }
+  }
+  double s = block_sum256<double>(ss, shd);
+  if (threadIdx.x == 0) sumsq_part[b] = s;
+}
+
 __global__ __launch_bounds__(256) void k_sample_finalize(SampleHdr* hdr, const uint32_t* blkoff,
                                                          uint32_t nblk, const double* sumsq_part,
                                                          uint32_t* wrank, uint32_t nwords) {
@@ -426,11 +631,6 @@ hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, doubl
   uint32_t* blkcnt = (uint32_t*)(ws + L.blkcnt);
   double* sumsq_part = (double*)(ws + L.sumsq_part);
   Entry* coo_l = (Entry*)(ws + L.coo_l);
-  uint32_t* rowptr = (uint32_t*)(ws + L.rowptr);
-  uint32_t* colptr = (uint32_t*)(ws + L.colptr);
-  uint32_t* csc_cnt = (uint32_t*)(ws + L.csc_cnt);
-  uint32_t* headrow = (uint32_t*)(ws + L.headrow);
-  Entry* coo_t = (Entry*)(ws + L.coo_t);
 
   uint64_t thresh = (uint64_t)std::floor(p * 4294967296.0);
   if (thresh > (1ull << 32)) thresh = 1ull << 32;
@@ -452,6 +652,57 @@ hipError_t launch_sample(const ShapeInfo& si, int x_is_f64, const void* X, doubl
   else
     hipLaunchKernelGGL(k_sample_compact<float>, dim3(si.nblk), dim3(kThreads), 0, st,
                        (const float*)X, si.N, bitmap, blkcnt, wrank, coo_l, cap, sumsq_part);
+  return launch_layouts(si, ws, L, st);
+}
+
+hipError_t launch_sample_slide(const ShapeInfo& si, int x_is_f64, const void* X, double p,
+                               uint64_t seed, uint64_t tick0, char* ws, const SampleLayout& L,
+                               uint64_t cap, const char* ws_prev, hipStream_t st) {
+  SampleHdr* hdr = (SampleHdr*)(ws + L.hdr);
+  uint64_t* bitmap = (uint64_t*)(ws + L.bitmap);
+  uint32_t* wrank = (uint32_t*)(ws + L.wrank);
+  uint32_t* blkcnt = (uint32_t*)(ws + L.blkcnt);
+  double* sumsq_part = (double*)(ws + L.sumsq_part);
+  Entry* coo_l = (Entry*)(ws + L.coo_l);
+  uint64_t thresh = (uint64_t)std::floor(p * 4294967296.0);
+  if (thresh > (1ull << 32)) thresh = 1ull << 32;
+  PrevSample pv{(const SampleHdr*)(ws_prev + L.hdr), (const uint64_t*)(ws_prev + L.bitmap),
+                (const uint32_t*)(ws_prev + L.wrank), (const Entry*)(ws_prev + L.coo_l)};
+  hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, hdr, p, thresh, cap, seed, tick0,
+                     (uint64_t)1);
+  const FastDiv fT = si.fdim[si.d - 1];
+  hipLaunchKernelGGL(k_sample_mask_slide, dim3(si.nblk), dim3(kThreads), 0, st, si.N, fT, thresh, seed,
+                     tick0, cap, pv, bitmap, blkcnt);
+  scan_u32(blkcnt, si.nblk, (uint32_t*)(ws + L.scan_tmp), st);
+  hipLaunchKernelGGL(k_word_ranks, dim3(si.nblk), dim3(kThreads), 0, st, bitmap, blkcnt, wrank);
+  const uint32_t T = si.dims[si.d - 1], nseries = si.N / T;
+  if (!x_is_f64)
+    hipLaunchKernelGGL(k_slide_copy_runs, dim3((nseries + 3) / 4), dim3(256), 0, st, nseries, T, tick0,
+                       seed, thresh, cap, pv, bitmap, wrank, blkcnt + si.nblk, coo_l);
+  if (x_is_f64)
+    hipLaunchKernelGGL(k_sample_compact_slide<double>, dim3(si.nblk), dim3(kThreads), 0, st,
+                       (const double*)X, si.N, fT, tick0, seed, thresh, pv, bitmap, blkcnt, wrank, coo_l,
+                       cap, sumsq_part);
+  else
+    hipLaunchKernelGGL(k_sample_compact_slide<float>, dim3(si.nblk), dim3(kThreads), 0, st,
+                       (const float*)X, si.N, fT, tick0, seed, thresh, pv, bitmap, blkcnt, wrank, coo_l,
+                       cap, sumsq_part);
+  return launch_layouts(si, ws, L, st);
+}
+
+// Kept count and status, then the CSR row pointers and the CSC copy.
+hipError_t launch_layouts(const ShapeInfo& si, char* ws, const SampleLayout& L, hipStream_t st) {
+  SampleHdr* hdr = (SampleHdr*)(ws + L.hdr);
+  uint64_t* bitmap = (uint64_t*)(ws + L.bitmap);
+  uint32_t* wrank = (uint32_t*)(ws + L.wrank);
+  uint32_t* blkcnt = (uint32_t*)(ws + L.blkcnt);
+  double* sumsq_part = (double*)(ws + L.sumsq_part);
+  Entry* coo_l = (Entry*)(ws + L.coo_l);
+  uint32_t* rowptr = (uint32_t*)(ws + L.rowptr);
+  uint32_t* colptr = (uint32_t*)(ws + L.colptr);
+  uint32_t* csc_cnt = (uint32_t*)(ws + L.csc_cnt);
+  uint32_t* headrow = (uint32_t*)(ws + L.headrow);
+  Entry* coo_t = (Entry*)(ws + L.coo_t);
   hipLaunchKernelGGL(k_sample_finalize, dim3(1), dim3(256), 0, st, hdr, blkcnt, si.nblk,
                      sumsq_part, wrank, si.nwords);
   hipLaunchKernelGGL(k_rowptr, dim3((si.MH + 1 + 255) / 256), dim3(256), 0, st, si, bitmap,

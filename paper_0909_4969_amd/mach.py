@@ -26,7 +26,7 @@ EXPORTED = (
     "mach_solver_workspace_bytes", "mach_hosvd", "mach_hooi_sweep", "mach_core",
     "mach_solver_reset", "mach_layout_info", "mach_sample_offsets",
     "mach_read_status", "mach_status_string", "mach_host_selftest",
-    "mach_timing_enable", "mach_timing_read", "mach_core_noalloc",
+    "mach_timing_enable", "mach_timing_read", "mach_core_noalloc", "mach_sample_ticks_slide",
 )
 
 
@@ -61,6 +61,7 @@ def _load():
         "mach_nnz_capacity": (U64, [SP, D]),
         "mach_sample": (I32, [SP, I32, P, D, U64, U64, P, SZ, U64, P]),
         "mach_sample_ticks": (I32, [SP, I32, P, D, U64, U64, P, SZ, U64, P]),
+        "mach_sample_ticks_slide": (I32, [SP, I32, P, D, U64, U64, P, P, SZ, U64, P]),
         "mach_solver_workspace_bytes": (SZ, [SP, IP, I32, U64]),
         "mach_hosvd": (I32, [P, U64, SP, IP, P, P, SZ, P]),
         "mach_hooi_sweep": (I32, [P, U64, SP, IP, P, I32, I32, P, SZ, P, P]),
@@ -191,10 +192,14 @@ class SampleWorkspace:
 
 
 def sample(X: torch.Tensor, p: float, seed: int, window_id: int, cap: int | None = None,
-           ws: SampleWorkspace | None = None, stream=None, tick0: int | None = None) -> SampleWorkspace:
+           ws: SampleWorkspace | None = None, stream=None, tick0: int | None = None,
+           prev: SampleWorkspace | None = None) -> SampleWorkspace:
     """MACH's coin toss over the device tensor X (float32 or float64).  With
     tick0, the coins are keyed on (seed, series, absolute tick) instead of
-    (seed, window_id, linear index): X's last mode holds ticks tick0, ..."""
+    (seed, window_id, linear index): X's last mode holds ticks tick0, ...;
+    with tick0 and prev (the sample of an earlier window of the same stream,
+    shape, seed, p and capacity), the measurements the two windows share
+    keep prev's coins and values (mach_sample_ticks_slide)."""
     if not X.is_cuda or not X.is_contiguous():
         raise ValueError("X must be a contiguous device tensor")
     dt = {torch.float32: MACH_F32, torch.float64: MACH_F64}.get(X.dtype)
@@ -209,6 +214,14 @@ def sample(X: torch.Tensor, p: float, seed: int, window_id: int, cap: int | None
             raise MachError("mach_sample_workspace_bytes", MACH_EINVAL)
         ws = SampleWorkspace(shape, cap, torch.empty(nb, dtype=torch.uint8, device=X.device))
     s = Shape.of(shape)
+    if prev is not None:
+        if tick0 is None:
+            raise ValueError("a slid window needs tick0")
+        _check("mach_sample_ticks_slide",
+               LIB.mach_sample_ticks_slide(ctypes.byref(s), dt, ctypes.c_void_p(X.data_ptr()), float(p),
+                                           int(seed), int(tick0), prev.ptr, ws.ptr, ws.buf.numel(), cap,
+                                           _stream(stream)))
+        return ws
     if tick0 is not None:
         _check("mach_sample_ticks", LIB.mach_sample_ticks(ctypes.byref(s), dt, ctypes.c_void_p(X.data_ptr()),
                                                           float(p), int(seed), int(tick0), ws.ptr,
@@ -322,8 +335,8 @@ class Decomposition:
         self.G = torch.zeros(self.ranks, dtype=torch.float64, device=device)
         self.norm2 = torch.zeros(1, dtype=torch.float64, device=device)
 
-    def sample(self, X, seed, window_id, stream=None, tick0=None):
-        sample(X, self.p, seed, window_id, ws=self.sw, stream=stream, tick0=tick0)
+    def sample(self, X, seed, window_id, stream=None, tick0=None, prev=None):
+        sample(X, self.p, seed, window_id, ws=self.sw, stream=stream, tick0=tick0, prev=prev)
 
     def hosvd(self, stream=None):
         hosvd(self.sw, self.ranks, self.solver, self.factors, stream=stream)

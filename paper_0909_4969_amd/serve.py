@@ -15,6 +15,10 @@ as soon as it is complete).  The engine
     its previous window, which stay resident: the time mode is updated first
     from them (a sweep that starts at the last mode), then full HOOI sweeps
     run (Alg. 2); a stream's first window is initialised by HOSVD;
+  * samples a window that carries its absolute first tick with stream coins,
+    from the stream's previous window's sample when they overlap (the shared
+    measurements keep their coins and kept values; only the new ticks are
+    tossed and read);
   * reports each window's latency (result ready - arrival).
 
 Argument marshalling and scheduling only: every step of a window runs in the
@@ -105,6 +109,10 @@ class Engine:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max(1, cfg.hip_streams))]
         self._load = [0] * len(self.streams)
         self.resident = {}        # stream_id -> (hosts, [A_host, A_metric]) float64 device tensors
+        # stream_id -> the last window's sample workspace, kept when its
+        # window carried an absolute tick: the stream's next window is
+        # sampled from it (shared measurements keep their coins and values)
+        self.prev_sample = {}
 
     # ---- memory ----------------------------------------------------------
     def footprint(self, shape) -> int:
@@ -135,7 +143,10 @@ class Engine:
             fit = torch.zeros(1, dtype=torch.float64, device=self.device)
             G = torch.empty(tuple(cfg.ranks), dtype=torch.float64, device=self.device)
             norm2 = torch.empty(1, dtype=torch.float64, device=self.device)
-            M.sample(win.X, cfg.p, win.seed, win.window_id, ws=sw, stream=s, tick0=win.tick0)
+            prev = self.prev_sample.get(win.stream_id) if win.tick0 is not None else None
+            if prev is not None and (prev.shape != shape or prev.cap != cap):
+                prev = None
+            M.sample(win.X, cfg.p, win.seed, win.window_id, ws=sw, stream=s, tick0=win.tick0, prev=prev)
             if warm:
                 factors = [res[1][0].clone(), res[1][1].clone(),
                            torch.zeros(shape[2], cfg.ranks[2], dtype=torch.float64, device=self.device)]
@@ -163,6 +174,8 @@ class Engine:
         w = job.win
         if self.cfg.warm_start:
             self.resident[w.stream_id] = (w.X.shape[0], [job.factors[0], job.factors[1]])
+        if w.tick0 is not None:
+            self.prev_sample[w.stream_id] = job.sw
         return WindowResult(w.req_id, w.stream_id, w.window_id, job.warm, nnz, float(job.fit.item()),
                             job.factors, job.G, w.arrival_s, job.admit_s, now_s, job.footprint)
 

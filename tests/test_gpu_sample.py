@@ -181,6 +181,94 @@ def test_overlapping_stream_windows_keep_the_same_measurements():
     assert ov[0] == ov[1]
 
 
+def _workspace_arrays(sw, shape, nnz):
+    """Everything the layouts hold, as host arrays, for bit-for-bit
+    comparison of two sample workspaces of the same shape and capacity."""
+    N = int(np.prod(shape))
+    nwords = ((N + 16383) // 16384) * 256
+    h, _ = S.head_split(shape)
+    MH = int(np.prod(shape[:h]))
+    MT = N // MH
+    out = {"bitmap": sw.u64("bitmap", nwords), "wrank": sw.u32("wrank", nwords + 1),
+           "rowptr": sw.u32("rowptr", MH + 1), "colptr": sw.u32("colptr", MT + 1)}
+    for which in ("coo_l", "coo_t"):
+        idx, val = sw.entries(which, nnz)
+        out[which + "_idx"], out[which + "_val"] = idx, val.view(np.uint32)
+    return out
+
+
+# (name, stream shape (series..., ticks), window T, first ticks of the
+# earlier and the new window, dtype, p, seed of the earlier window)
+SLIDES = [
+    ("forward-7x5x333", (7, 5), 333, (1000, 1100), np.float32, 0.3, 61),
+    ("forward-hop1-32x16x2048", (32, 16), 2048, (5000, 5001), np.float32, 0.1, 62),
+    ("backward-16x8x600", (16, 8), 600, (3000, 2700), np.float32, 0.2, 63),
+    ("no-overlap-16x8x600", (16, 8), 600, (0, 600), np.float32, 0.2, 64),
+    ("other-seed-16x8x600", (16, 8), 600, (0, 150), np.float32, 0.2, None),
+    ("f64-9x64x500", (9, 64), 500, (10, 210), np.float64, 0.25, 65),
+]
+
+
+@pytest.mark.parametrize("name,series,T,ticks,dt,p,seed0", SLIDES, ids=[x[0] for x in SLIDES])
+def test_slid_window_equals_fresh_toss(name, series, T, ticks, dt, p, seed0):
+    """mach_sample_ticks_slide from an earlier window's sample against a fresh
+    mach_sample_ticks of the new window: every array of the workspace bit for
+    bit, the kept count and the sum of squares; and the mask and kept list
+    against the oracle's tick-keyed coins.  "other-seed" gives the earlier
+    window another seed, so nothing may be reused (fresh toss)."""
+    import torch
+    from paper_0909_4969_amd import mach as M
+    seed = 66
+    t_prev, t_new = ticks
+    lo = min(t_prev, t_new)
+    rng = np.random.default_rng(sum(map(ord, name)))
+    stream = rng.standard_normal(tuple(series) + (max(t_prev, t_new) + T - lo,)).astype(dt)
+    X_prev = np.ascontiguousarray(stream[..., t_prev - lo:t_prev - lo + T])
+    X_new = np.ascontiguousarray(stream[..., t_new - lo:t_new - lo + T])
+    shape = X_new.shape
+    cap = M.nnz_capacity(shape, p)
+    say("slide", name, shape, ticks, p)
+    prev = M.sample(torch.from_numpy(X_prev).cuda(), p, seed if seed0 is not None else seed + 1, 0,
+                    cap=cap, tick0=t_prev)
+    Xd = torch.from_numpy(X_new).cuda()
+    slid = M.sample(Xd, p, seed, 0, cap=cap, tick0=t_new, prev=prev)
+    fresh = M.sample(Xd, p, seed, 0, cap=cap, tick0=t_new)
+    st_s, nnz_s, ss_s = slid.status()
+    st_f, nnz_f, ss_f = fresh.status()
+    assert st_s == 0 and st_f == 0
+    assert nnz_s == nnz_f and ss_s == ss_f
+    a, b = _workspace_arrays(slid, shape, nnz_s), _workspace_arrays(fresh, shape, nnz_f)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    coo = O.sample_coo_ticks(X_new, p, seed, t_new)
+    assert nnz_s == coo.nnz
+    np.testing.assert_array_equal(a["coo_l_idx"], coo.idx)
+    np.testing.assert_array_equal(a["coo_l_val"], coo.val.view(np.uint32))
+
+
+def test_slid_monitoring_window():
+    """A 128 x 16 x 16384 window slid by 2048 ticks along its stream: bit for
+    bit a fresh toss (float32 input, p = 0.1)."""
+    import torch
+    from paper_0909_4969_amd import mach as M
+    rng = np.random.default_rng(71)
+    T, hop, p, seed = 16384, 2048, 0.1, 72
+    stream = torch.from_numpy(rng.standard_normal((128, 16, T + hop)).astype(np.float32)).cuda()
+    Xa = stream[..., :T].contiguous()
+    Xb = stream[..., hop:].contiguous()
+    cap = M.nnz_capacity((128, 16, T), p)
+    say("slide monitoring window", hop)
+    prev = M.sample(Xa, p, seed, 0, cap=cap, tick0=40000)
+    slid = M.sample(Xb, p, seed, 0, cap=cap, tick0=40000 + hop, prev=prev)
+    fresh = M.sample(Xb, p, seed, 0, cap=cap, tick0=40000 + hop)
+    st_s, nnz_s, ss_s = slid.status()
+    st_f, nnz_f, ss_f = fresh.status()
+    assert st_s == 0 and st_f == 0 and nnz_s == nnz_f and ss_s == ss_f
+    a, b = _workspace_arrays(slid, (128, 16, T), nnz_s), _workspace_arrays(fresh, (128, 16, T), nnz_f)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
 def test_tick_keyed_window_through_hosvd():
     """The solver on a tick-keyed sample matches the oracle's HOSVD of the
     same sampled tensor."""
