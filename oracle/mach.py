@@ -39,6 +39,11 @@ Readings where the paper is silent or ambiguous:
       the factors of Alg. 1 and 2, are not determined.  Such a sample is
       degenerate (DegenerateSample); one with a non-finite entry is rejected
       (ValueError).
+  R11 Tucker-n (Section 2.1: compressing n of the d modes): a mode given
+      rank 0 is not compressed; its factor is the identity (None here), HOOI
+      does not update it, and the core keeps that mode's full size.  HOSVD
+      and HOOI of the other modes are unchanged (Alg. 1/2 with the identity
+      in the products).
 
 Parity status: every function below is pinned by tests/test_oracle_*.py,
 except `theorem1_hypotheses` (report-only: its conditions are checked, the
@@ -298,9 +303,13 @@ def check_sample(Xh: np.ndarray) -> None:
 
 
 def hosvd_factors(Xh: np.ndarray, ranks):
-    """A^(i) = r_i leading left singular vectors of X-hat_(i), i = 1..d (Alg. 1)."""
+    """A^(i) = r_i leading left singular vectors of X-hat_(i), i = 1..d (Alg. 1).
+
+    Tucker-n (Section 2.1: compressing n of the d modes): a mode with r_i = 0
+    is left uncompressed; its factor is None, i.e. the identity, which every
+    mode product here skips."""
     check_sample(Xh)
-    return [leading_left_singular_vectors(unfold(Xh, i), ranks[i])[0]
+    return [leading_left_singular_vectors(unfold(Xh, i), ranks[i])[0] if ranks[i] > 0 else None
             for i in range(Xh.ndim)]
 
 
@@ -316,9 +325,11 @@ def hooi_sweep(Xh: np.ndarray, factors, ranks, first_mode: int = 0):
     the update of mode n, ||G||^2 = sum of the top r_n squared singular values
     of Y_(n) (norm invariance, eq. eqa)."""
     check_sample(Xh)
-    A = [np.array(a, dtype=np.float64) for a in factors]
+    A = [np.array(a, dtype=np.float64) if a is not None else None for a in factors]
     trace = []
     for n in range(first_mode, Xh.ndim):
+        if ranks[n] == 0:        # uncompressed mode (Tucker-n): identity, not updated
+            continue
         Y = ttm_chain(Xh, A, n)
         U, s = leading_left_singular_vectors(unfold(Y, n), ranks[n])
         A[n] = U
