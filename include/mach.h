@@ -143,7 +143,17 @@ mach_status mach_sample_ticks_slide(const mach_shape* s, mach_dtype x_dtype, con
 /* Bytes of the solver workspace for shape s and ranks R_1..R_d (host array
  * of d int32).  prec is the precision mach_hooi_sweep will be called with
  * (MACH_F32, MACH_BF16 or MACH_FP8E4M3; the workspace serves all three).
- * Returns 0 if the arguments are invalid or prec is not supported. */
+ * Returns 0 if the arguments are invalid or prec is not supported.
+ *
+ * Tucker-n (Section 2.1: compressing n of the d modes): R_d = 0 leaves the
+ * last mode uncompressed - its factor is the identity, HOSVD and HOOI do
+ * not compute or update it (its A_dev entry may be NULL), and the core is
+ * R_1 x ... x R_{d-1} x I_d.  Supported when the last mode is the layouts'
+ * only tail mode (mach_layout_info gives h = d - 1, e.g. hosts x metrics x
+ * time, sensors x types x time) and every other mode's Gram is on the row
+ * side (I_n <= prod of the other modes' ranks, the uncompressed mode
+ * counting with I_d); else 0.  The sweep then works on the dense sampled
+ * tensor (4 N bytes of the workspace). */
 size_t mach_solver_workspace_bytes(const mach_shape* s, const int32_t* ranks,
                                    mach_dtype prec, uint64_t nnz_cap);
 
@@ -154,7 +164,9 @@ size_t mach_solver_workspace_bytes(const mach_shape* s, const int32_t* ranks,
  * shape.  A_dev is a host array of d device pointers, each I_n x R_n
  * float64 row-major, written.  nnz_cap is the capacity ws_sample was built
  * with (it fixes where the sparse arrays sit).  Requires
- * 1 <= R_n <= min(I_n, N / I_n, 16) and d <= 4.  Resets the solver
+ * 1 <= R_n <= min(I_n, N / I_n, 16) and d <= 4, except for an uncompressed
+ * last mode (R_d = 0, see mach_solver_workspace_bytes), whose A_dev entry
+ * may be NULL and is not written.  Resets the solver
  * workspace first.  The last mode's HOSVD runs on an auxiliary HIP stream
  * (one per caller stream and device, created on the first call, default
  * priority, kept for the life of the process), forked from and joined into
@@ -188,7 +200,9 @@ mach_status mach_hosvd(const void* ws_sample, uint64_t nnz_cap, const mach_shape
  * double it points to receives 1 - ||Xhat - G x A|| / ||Xhat|| after the
  * last update (with ||Xhat - G x A||^2 = ||Xhat||^2 - ||G||^2).
  * nnz_cap as for mach_hosvd.  Requires 1 <= R_n <= min(I_n, prod_{k != n}
- * R_k, 16) and d <= 4. */
+ * R_k, 16) and d <= 4; with an uncompressed last mode (R_d = 0) the sweep
+ * updates modes first_mode..d-2 (first_mode <= d - 2) and the fit is taken
+ * after mode d-1's update. */
 mach_status mach_hooi_sweep(const void* ws_sample, uint64_t nnz_cap, const mach_shape* s,
                             const int32_t* ranks, double* const* A_dev, mach_dtype prec,
                             int32_t first_mode, void* ws, size_t ws_bytes, double* fit_dev,
@@ -196,7 +210,8 @@ mach_status mach_hooi_sweep(const void* ws_sample, uint64_t nnz_cap, const mach_
 
 /* The core G = Xhat x_1 A^(1)T ... x_d A^(d)T (eq. eqcore), float64, C
  * order R_1 x ... x R_d, written to G_dev; ||G||^2 to *core_norm2_dev if
- * not NULL.  Uses the factors in A_dev. */
+ * not NULL.  Uses the factors in A_dev.  With an uncompressed last mode
+ * (R_d = 0) the core is R_1 x ... x R_{d-1} x I_d (no product along it). */
 mach_status mach_core(const void* ws_sample, uint64_t nnz_cap, const mach_shape* s,
                       const int32_t* ranks, double* const* A_dev, double* G_dev,
                       double* core_norm2_dev, void* ws, size_t ws_bytes, void* stream);

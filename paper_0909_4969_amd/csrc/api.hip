@@ -233,22 +233,41 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   SolverLayout S;
   std::memset(&S, 0, sizeof(S));
   const int d = si.d, h = si.h;
+  // Tucker-n: the last mode may be left uncompressed (rank 0, identity
+  // factor) when it is the only tail mode; its "rank" is then its size.
+  const int ident = ranks[d - 1] == 0;
+  if (ident && d - h != 1) return false;
+  S.ident_last = ident;
+  auto Reff = [&](int k) -> uint32_t { return (ident && k == d - 1) ? si.dims[k] : (uint32_t)ranks[k]; };
   uint64_t prodR = 1;
   for (int k = 0; k < d; ++k) {
-    if (ranks[k] < 1 || ranks[k] > kMaxRank || (uint32_t)ranks[k] > si.dims[k]) return false;
-    prodR *= (uint64_t)ranks[k];
+    if (!(ident && k == d - 1) &&
+        (ranks[k] < 1 || ranks[k] > kMaxRank || (uint32_t)ranks[k] > si.dims[k]))
+      return false;
+    prodR *= (uint64_t)Reff(k);
   }
   S.KT = 1;
   S.KH = 1;
-  for (int k = 0; k < d; ++k) (k < h ? S.KH : S.KT) *= (uint32_t)ranks[k];
+  for (int k = 0; k < d; ++k) (k < h ? S.KH : S.KT) *= Reff(k);
   uint32_t smax_sweep = 1, zrows = kBlock, imax = 1, hs_iside_max = 1;
   size_t gmax = 1;
   for (int k = 0; k < d; ++k) {
     ModePlan& m = S.mp[k];
     m.I = si.dims[k];
-    m.R = (uint32_t)ranks[k];
+    m.R = Reff(k);
+    if (prodR / m.R >= (1ull << 31)) return false;
     m.K = (uint32_t)(prodR / m.R);
+    if (ident && k == d - 1) {     // not updated: no Gram, no eigen state, no HOSVD
+      m.kside = 0;
+      m.s = 0;
+      m.contract_mode = -1;
+      S.hosvd_s[k] = 0;
+      continue;
+    }
     m.kside = m.K < m.I;
+    // the column-side warm start maps eigenbases through the other modes'
+    // factors, which an identity mode does not have
+    if (ident && m.kside) return false;
     m.s = m.kside ? m.K : m.I;
     if (m.R > m.s) return false;
     if (m.kside && m.I > 262144) return false;
@@ -267,7 +286,7 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   }
   // Views of Y_k (see solver.h).
   const uint32_t* I = si.dims;
-  auto R = [&](int k) { return (uint32_t)ranks[k]; };
+  auto R = Reff;
   if (h == 1) {
     S.mp[0].O = 1;
     S.mp[0].Q = S.KT;
@@ -326,7 +345,7 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   for (int k = 0; k < d; ++k) S.af16[k] = take((size_t)I[k] * 16 * 2);
   S.TH = take((size_t)si.MH * S.KT * 4);
   S.TT = take((size_t)si.MT * S.KH * 4);
-  if (d - h == 1 && (size_t)I[d - 1] * 16 * 4 > kTiledFactorBytes) {
+  if (d - h == 1 && !ident && (size_t)I[d - 1] * 16 * 4 > kTiledFactorBytes) {
     const size_t nt = (I[d - 1] + kTileTicksMin - 1) / kTileTicksMin;
     S.tpart = take(nt * si.MH * 16 * 4);
   }
@@ -334,6 +353,7 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
     ModePlan& m = S.mp[k];
     if (m.contract_mode >= 0) m.ybuf = take((size_t)m.I * m.K * 4);
     else m.ybuf = k < h ? S.TH : S.TT;
+    if (ident && k == d - 1) continue;
     if (m.s <= (uint32_t)kSmallEig) {
       // eigenbasis (s x s), or the I x 16 block of the short-side iteration
       m.V = take(std::max((size_t)m.s * m.s, m.kside ? (size_t)m.I * 16 : 0) * 8);
@@ -462,7 +482,7 @@ mach_status prepare(const void* ws_sample, uint64_t cap, const mach_shape* s, co
   if (ws_bytes < P->SL.total) return MACH_ENOMEM;
   if (((uintptr_t)ws & 255) || ((uintptr_t)ws_sample & 255)) return MACH_EINVAL;
   for (int k = 0; k < P->si.d; ++k)
-    if (!A[k]) return MACH_EINVAL;
+    if (!A[k] && !(P->SL.ident_last && k == P->si.d - 1)) return MACH_EINVAL;
   P->L = sample_layout(P->si, cap);
   P->sp = sparse_ptrs((const char*)ws_sample, P->L);
   return MACH_OK;
@@ -539,7 +559,8 @@ mach_status mach_hosvd(const void* ws_sample, uint64_t nnz_cap, const mach_shape
   hipStream_t st = (hipStream_t)stream;
   char* w = (char*)ws;
   if (launch_solver_init(P.SL, w, st) != hipSuccess) return MACH_EDEVICE;
-  const int d = P.si.d;
+  // modes with factors (an uncompressed last mode has none)
+  const int d = P.SL.ident_last ? P.si.d - 1 : P.si.d;
   // The modes' HOSVDs are independent: the last one (usually the largest
   // Gram) runs on an auxiliary stream with its own scratch, forked from and
   // joined back into `st` by events, beside the others on `st`.
@@ -571,10 +592,12 @@ mach_status mach_hooi_sweep(const void* ws_sample, uint64_t nnz_cap, const mach_
   Prepared P;
   mach_status rc = prepare(ws_sample, nnz_cap, s, ranks, A_dev, ws, ws_bytes, &P);
   if (rc != MACH_OK) return rc;
-  if (first_mode < 0 || first_mode >= P.si.d) return MACH_EINVAL;
+  // the last mode updated: an uncompressed last mode keeps its identity
+  const int last = P.SL.ident_last ? P.si.d - 2 : P.si.d - 1;
+  if (first_mode < 0 || first_mode > last) return MACH_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   char* w = (char*)ws;
-  const int d = P.si.d, h = P.si.h;
+  const int d = last + 1, h = P.si.h;
   const double density = (double)nnz_cap / (double)P.si.N;
   const SampleHdr* hdr = P.sp.hdr;
   bool ok = launch_factors_to_f32(P.si, P.SL, w, A_dev, ranks, hdr, st) == hipSuccess;
@@ -587,12 +610,13 @@ mach_status mach_hooi_sweep(const void* ws_sample, uint64_t nnz_cap, const mach_
     }
     tail0 = h;
   }
-  ok = ok && launch_contract_head(P.si, P.sp, P.SL, w, ranks, density, bf16, st) == hipSuccess;
+  if (tail0 < d)
+    ok = ok && launch_contract_head(P.si, P.sp, P.SL, w, ranks, density, bf16, st) == hipSuccess;
   for (int k = tail0; k < d && ok; ++k) {
     ok = launch_form_y(P.si, P.SL, w, k, hdr, st) == hipSuccess;
     ok = ok && launch_mode_update(P.si, P.SL, w, k, A_dev[k], prec, hdr, st) == hipSuccess;
   }
-  if (ok && fit_dev) ok = launch_fit(P.SL, w, d - 1, hdr, fit_dev, st) == hipSuccess;
+  if (ok && fit_dev) ok = launch_fit(P.SL, w, last, hdr, fit_dev, st) == hipSuccess;
   return ok ? MACH_OK : MACH_EDEVICE;
 }
 
@@ -656,6 +680,7 @@ bool make_core_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout* o
   std::memset(&S, 0, sizeof(S));
   S.KT = full.KT;
   S.KH = full.KH;
+  S.ident_last = full.ident_last;
   for (int k = 0; k < si.d; ++k) {
     S.mp[k] = full.mp[k];
     S.mp[k].ybuf = S.mp[k].V = S.mp[k].lam = S.mp[k].Q64 = 0;
@@ -690,10 +715,10 @@ mach_status mach_core_noalloc(const void* ws_sample, uint64_t nnz_cap, const mac
   if (si.d > 4) return MACH_EUNSUPPORTED;
   if (nnz_cap < 1 || nnz_cap > (1ull << 31)) return MACH_EINVAL;
   if ((uintptr_t)ws_sample & 255) return MACH_EINVAL;
-  for (int k = 0; k < si.d; ++k)
-    if (!A_dev[k]) return MACH_EINVAL;
   SolverLayout SL;
   if (!make_core_layout(si, ranks, &SL)) return MACH_EINVAL;
+  for (int k = 0; k < si.d; ++k)
+    if (!A_dev[k] && !(SL.ident_last && k == si.d - 1)) return MACH_EINVAL;
   if (SL.total > kCoreScratchBytes) return MACH_ENOMEM;
   char* w = (char*)scratch_ptr();
   if (!w) return MACH_EDEVICE;

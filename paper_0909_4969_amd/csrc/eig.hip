@@ -1679,6 +1679,18 @@ __global__ __launch_bounds__(256) void k_core(const float* __restrict__ Y, uint3
   if (threadIdx.x == 0) G[e] = acc / hdr->p;
 }
 
+// G[q * MT + c] = TT[c * KH + q] / p: the core of a Tucker-n decomposition
+// whose single tail mode is uncompressed (C order R_1 x .. x R_h x MT).
+__global__ __launch_bounds__(256) void k_core_ident(const float* __restrict__ TT, uint32_t MT, uint32_t KH,
+                                                    double* __restrict__ G, const SampleHdr* hdr,
+                                                    const int32_t* st) {
+  if (hdr->status != 0 || *st != 0) return;
+  const uint32_t e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= MT * KH) return;
+  const uint32_t q = e / MT, c = e - q * MT;
+  G[e] = (double)TT[(size_t)c * KH + q] / hdr->p;
+}
+
 __global__ __launch_bounds__(256) void k_norm2(const double* __restrict__ G, uint32_t n, double* out,
                                                const SampleHdr* hdr, const int32_t* st) {
   if (hdr->status != 0 || *st != 0) return;
@@ -2148,6 +2160,14 @@ hipError_t launch_fit(const SolverLayout& SL, char* ws, int k, const SampleHdr* 
 hipError_t launch_core(const ShapeInfo& si, const SolverLayout& SL, char* ws, const double* A_last,
                        double* G, double* norm2, const SampleHdr* hdr, hipStream_t st) {
   const ModePlan& m = SL.mp[si.d - 1];
+  if (SL.ident_last) {   // the last mode uncompressed: G is TT transposed, times 1/p
+    const uint32_t n = SL.KH * si.MT;
+    const int32_t* stp = (const int32_t*)(ws + SL.status);
+    hipLaunchKernelGGL(k_core_ident, dim3(cdiv(n, 256)), dim3(256), 0, st, (const float*)(ws + SL.TT),
+                       si.MT, SL.KH, G, hdr, stp);
+    if (norm2) hipLaunchKernelGGL(k_norm2, dim3(1), dim3(256), 0, st, G, n, norm2, hdr, stp);
+    return hipGetLastError();
+  }
   uint32_t n = m.O * m.Q * m.R;
   const int32_t* stp = (const int32_t*)(ws + SL.status);
   hipLaunchKernelGGL(k_core, dim3(n), dim3(256), 0, st, (const float*)(ws + m.ybuf), m.O,

@@ -82,6 +82,7 @@ struct SolverLayout {
   // there is none (d == 1).
   size_t laneb[17];
   size_t total;
+  int ident_last;                        // the last mode is left uncompressed (Tucker-n)
   ModePlan mp[kMaxD];
   uint32_t KT, KH, hosvd_s[kMaxD];
   int hosvd_kside[kMaxD];

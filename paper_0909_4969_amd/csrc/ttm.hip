@@ -609,9 +609,49 @@ __global__ void k_factors_to_f32(F32Args a, const SampleHdr* hdr) {
 
 }  // namespace
 
+// TH = Xhat (unscaled, float32, C order) when the single tail mode is left
+// uncompressed (its factor is the identity, so the head-row pass contracts
+// nothing): one thread per bitmap word writes its 64 entries, the kept
+// values taken in order from the word's rank.
+__global__ __launch_bounds__(256) void k_densify(const uint64_t* __restrict__ bitmap,
+                                                 const uint32_t* __restrict__ wrank,
+                                                 const Entry* __restrict__ coo, uint32_t N,
+                                                 float* __restrict__ out, const SampleHdr* hdr,
+                                                 const int32_t* st_solver) {
+  if (hdr->status != 0 || *st_solver != 0) return;
+  const uint32_t w = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t l0 = w * 64u;
+  if (l0 >= N) return;
+  const uint64_t word = bitmap[w];
+  uint32_t r = wrank[w];
+#pragma unroll 4
+  for (uint32_t b = 0; b < 64; b += 4) {
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool kept = (word >> (b + k)) & 1ull;
+      v[k] = kept ? coo[r].v : 0.f;
+      r += kept ? 1u : 0u;
+    }
+    if (l0 + b + 3 < N) {
+      *reinterpret_cast<float4*>(out + l0 + b) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (l0 + b + k < N) out[l0 + b + k] = v[k];
+    }
+  }
+}
+
 hipError_t launch_contract_tail(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
                                 char* ws, const int32_t* ranks, double density, int bf16,
                                 hipStream_t st) {
+  if (SL.ident_last) {
+    const uint32_t nw = (si.N + 63) / 64;
+    hipLaunchKernelGGL(k_densify, dim3((nw + 255) / 256), dim3(256), 0, st, sp.bitmap, sp.wrank, sp.coo_l,
+                       si.N, (float*)(ws + SL.TH), sp.hdr, (const int32_t*)(ws + SL.status));
+    return hipGetLastError();
+  }
   if (bf16) {
     hipError_t e = to_bf16(si, SL, ws, si.h, si.d, sp.hdr, st);
     if (e != hipSuccess) return e;

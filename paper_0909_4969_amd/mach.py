@@ -107,7 +107,8 @@ def _ranks(ranks):
 
 
 def _ptr_array(tensors):
-    arr = (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+    arr = (ctypes.c_void_p * len(tensors))(*[t.data_ptr() if t is not None and t.numel() else None
+                                              for t in tensors])
     return arr
 
 
@@ -242,8 +243,15 @@ def solver_workspace(shape, ranks, cap, device="cuda") -> torch.Tensor:
 
 def _factors_ok(factors, shape, ranks):
     for A, I, R in zip(factors, shape, ranks):
+        if R == 0:          # uncompressed mode (identity factor): passed as NULL
+            continue
         if A.dtype != torch.float64 or not A.is_cuda or tuple(A.shape) != (I, R) or not A.is_contiguous():
             raise ValueError("factors must be contiguous float64 device tensors of shape (I_n, R_n)")
+
+
+def core_shape(shape, ranks):
+    """Shape of the core: R_n, or I_n for an uncompressed mode (R_n = 0)."""
+    return tuple(int(r) if r > 0 else int(I) for I, r in zip(shape, ranks))
 
 
 def hosvd(sw: SampleWorkspace, ranks, solver: torch.Tensor, factors=None, stream=None):
@@ -293,7 +301,7 @@ def core(sw: SampleWorkspace, ranks, factors, solver: torch.Tensor, G=None, norm
     _factors_ok(factors, sw.shape, ranks)
     dev = sw.buf.device
     if G is None:
-        G = torch.empty(tuple(ranks), dtype=torch.float64, device=dev)
+        G = torch.empty(core_shape(sw.shape, ranks), dtype=torch.float64, device=dev)
     if norm2 is None:
         norm2 = torch.empty(1, dtype=torch.float64, device=dev)
     s = Shape.of(sw.shape)
@@ -332,7 +340,7 @@ class Decomposition:
         self.factors = [torch.zeros(I, R, dtype=torch.float64, device=device)
                         for I, R in zip(self.shape, self.ranks)]
         self.fit = torch.zeros(1, dtype=torch.float64, device=device)
-        self.G = torch.zeros(self.ranks, dtype=torch.float64, device=device)
+        self.G = torch.zeros(core_shape(self.shape, self.ranks), dtype=torch.float64, device=device)
         self.norm2 = torch.zeros(1, dtype=torch.float64, device=device)
 
     def sample(self, X, seed, window_id, stream=None, tick0=None, prev=None):

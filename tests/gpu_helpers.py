@@ -23,9 +23,11 @@ def oracle_sweep_with_gaps(Xh, factors, ranks, first_mode=0, sing=None):
     """One oracle HOOI sweep that also returns, per updated mode, the
     relative eigengap and the Davis-Kahan FP32 bound of Y_(n); with a dict
     `sing`, also the singular values of each Y_(n) in it."""
-    A = [np.array(a, dtype=np.float64) for a in factors]
+    A = [np.array(a, dtype=np.float64) if a is not None else None for a in factors]
     gaps, dk = {}, {}
     for n in range(first_mode, Xh.ndim):
+        if ranks[n] == 0:       # uncompressed mode: identity, not updated
+            continue
         Yn = O.unfold(O.ttm_chain(Xh, A, n), n)
         gaps[n] = O.eigengap(Yn, ranks[n])
         dk[n] = O.davis_kahan_bound(Yn, ranks[n], 2.0 ** -24)
@@ -86,6 +88,8 @@ def project(T, factors):
     out with tensordot; mode n of the result has size R_n)."""
     R = np.asarray(T, np.float64)
     for n, A in enumerate(factors):
+        if A is None:       # uncompressed mode: identity
+            continue
         R = np.moveaxis(np.tensordot(np.asarray(A, np.float64), R, axes=(0, n)), 0, n)
     return R
 
@@ -105,6 +109,8 @@ def load_factors(dec, factors):
     that a device step and an oracle step start from the same input."""
     import torch
     for f, a in zip(dec.factors, factors):
+        if a is None:       # uncompressed mode: no device factor
+            continue
         f.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)))
 
 

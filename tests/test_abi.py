@@ -130,3 +130,17 @@ def test_layout_split_follows_the_stated_rule(M):
     for shape in shapes:
         assert M.layout_info(shape) == S.head_split(shape), shape
 
+
+
+def test_tucker2_layout_rules(M):
+    """An uncompressed last mode (rank 0) is accepted when it is the single
+    tail mode and every other mode's Gram is on the row side."""
+    assert M.solver_workspace_bytes((128, 16, 16384), (8, 4, 0), 1000) > 0
+    assert M.solver_workspace_bytes((54, 4, 5385), (5, 2, 0), 1000) > 0
+    assert M.solver_workspace_bytes((200, 300), (6, 0), 1000) > 0
+    # two tail modes, a column-side mode, a zero rank elsewhere
+    assert M.solver_workspace_bytes((64, 64, 64, 256), (10, 10, 10, 0), 1000) == 0
+    assert M.solver_workspace_bytes((600, 12, 12), (10, 10, 0), 1000) == 0
+    assert M.solver_workspace_bytes((128, 16, 16384), (0, 4, 16), 1000) == 0
+    # the workspace holds the dense sampled tensor
+    assert M.solver_workspace_bytes((128, 16, 16384), (8, 4, 0), 1000) >= 4 * 128 * 16 * 16384
