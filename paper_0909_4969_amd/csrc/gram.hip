@@ -599,7 +599,7 @@ hipError_t launch_gram_tail_sparse(const ShapeInfo& si, const SparsePtrs& sp, co
 //   float32  v_mfma_f32_16x16x4_f32      (4 summation indices per step)
 //   bfloat16 v_mfma_f32_16x16x16_bf16    (16; round to nearest even)
 //   e4m3     v_mfma_f32_16x16x32_fp8_fp8 (32; each staged RB x CW tile is
-//            scaled by amax / 448 and rounded to nearest even, saturating)
+//            scaled by amax / 448, rounded to nearest even, saturating)
 // Products accumulate in float32 over runs of 32 summation indices and in
 // float64 across runs (times the two tiles' scales for e4m3).  Partials go to
 // part[(x X + y) nslice + slice] for every x, y < X (both triangles).
@@ -619,26 +619,15 @@ struct YGramArgs {
 };
 
 // OCP float8 e4m3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits;
-// largest finite 448) of a float32, rounded to nearest even and saturated
-// at +-448; subnormals are multiples of 2^-9.
-__device__ __forceinline__ uint32_t to_e4m3(float f) {
-  const uint32_t sign = (__float_as_uint(f) >> 24) & 0x80u;
-  const float a = fabsf(f);
-  if (!(a < 448.f)) return sign | 0x7Eu;
-  if (a >= 0.015625f) {               // normal: a >= 2^-6
-    const uint32_t ua = __float_as_uint(a);
-    int e = (int)(ua >> 23) - 127;
-    const uint32_t mant = ua & 0x7FFFFFu;
-    uint32_t r = mant >> 20;
-    const uint32_t rem = mant & 0xFFFFFu;
-    if (rem > 0x80000u || (rem == 0x80000u && (r & 1u))) ++r;
-    if (r == 8u) {
-      r = 0u;
-      ++e;
-    }
-    return sign | ((uint32_t)(e + 7) << 3) | r;
-  }
-  return sign | (uint32_t)rintf(a * 512.f);   // 0..8 (8 is 2^-6, the smallest normal)
+// largest finite 448) of four float32 values, rounded to nearest even and
+// saturated at +-448, packed into 32 bits (first value in the low byte).
+// gfx950's v_cvt_pk_fp8_f32 rounds to nearest even into this format but
+// does not saturate, so the values are clamped first.
+__device__ __forceinline__ uint32_t to_e4m3x4(float a, float b, float c, float d) {
+  auto cl = [](float x) { return fminf(fmaxf(x, -448.f), 448.f); };
+  int pk = __builtin_amdgcn_cvt_pk_fp8_f32(cl(a), cl(b), 0, false);
+  pk = __builtin_amdgcn_cvt_pk_fp8_f32(cl(c), cl(d), pk, true);
+  return (uint32_t)pk;
 }
 
 __device__ __forceinline__ uint32_t to_bf16(float f) {
@@ -767,12 +756,12 @@ __global__ __launch_bounds__(256) void k_gram_y_mfma(YGramArgs a) {
           }
           acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(oa, ob, acc[u], 0, 0, 0);
         } else {
-          uint64_t oa = 0, ob = 0;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            oa |= (uint64_t)to_e4m3(ra[8 * lk + q] * ia) << (8 * q);
-            ob |= (uint64_t)to_e4m3(rb[8 * lk + q] * ib) << (8 * q);
-          }
+          const float* pa = ra + 8 * lk;
+          const float* pb = rb + 8 * lk;
+          const uint64_t oa = (uint64_t)to_e4m3x4(pa[0] * ia, pa[1] * ia, pa[2] * ia, pa[3] * ia) |
+                              ((uint64_t)to_e4m3x4(pa[4] * ia, pa[5] * ia, pa[6] * ia, pa[7] * ia) << 32);
+          const uint64_t ob = (uint64_t)to_e4m3x4(pb[0] * ib, pb[1] * ib, pb[2] * ib, pb[3] * ib) |
+                              ((uint64_t)to_e4m3x4(pb[4] * ib, pb[5] * ib, pb[6] * ib, pb[7] * ib) << 32);
           acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)oa, (long)ob, acc[u], 0, 0, 0);
         }
       }
