@@ -133,8 +133,7 @@ template <int NP>
 struct JacLds {
   double A[NP][NP + 1];                 // the matrix being diagonalised
   double V[NP][NP + 1];                 // accumulated rotations
-  double W[NP][NP + 1];                 // scratch (warm-start products)
-  double rc[NP / 2], rs[NP / 2], rt[NP / 2];
+  double W[NP][NP + 1];                 // scratch (warm-start products; second copy of A in Jacobi)
   int rk[NP];
   double red[2][16];
 };
@@ -233,91 +232,150 @@ __device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin,
   __syncthreads();
 }
 
+// Jacobi rotation of the pair (p, q) of a symmetric matrix (Golub & Van
+// Loan, Sec. 8.5, sym.schur2): t = tan of the smaller angle that zeroes
+// a_pq, c = cos, s = sin.  t is formed in float32 from the pair scaled by a
+// power of two, with hardware reciprocals (its rounding leaves a_pq at
+// about 1e-7 of its size, which the next sweeps remove like any other
+// off-diagonal entry); c and s follow from t in float64, so the rotation is
+// orthogonal to float64 rounding.  The identity when a_pq is negligible
+// against the diagonal.  No branches: every lane runs the same instructions.
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double* c, double* s) {
+  const bool act = fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * (fabs(app) + fabs(aqq));
+  const int e = ilogb(act ? apq : 1.0);
+  const float num = (float)ldexp(aqq - app, -e), den = (float)ldexp(2.0 * apq, -e);
+  const float th = num * __builtin_amdgcn_rcpf(den);
+  const float ath = fabsf(th);
+  const float tbig = 0.5f * __builtin_amdgcn_rcpf(th);
+  const float tsml = __builtin_amdgcn_rcpf(ath + __builtin_amdgcn_sqrtf(fmaf(th, th, 1.0f)));
+  const float t = ath > 1e15f ? tbig : copysignf(tsml, th);
+  const double td = act ? (double)t : 0.0;
+  const double cc = act ? rsqrt(fma(td, td, 1.0)) : 1.0;
+  *c = cc;
+  *s = td * cc;
+}
+
 // Cyclic two-sided Jacobi on L.A (n x n padded to NP, symmetric),
-// accumulating rotations into L.V.  Each round applies NP/2 disjoint
-// rotations (round-robin ordering): their angles are computed by the first
-// NP/2 threads and staged in LDS, then every 2x2 block and every row pair of
-// V is updated in place by one thread.
+// accumulating rotations into L.V.  Each round applies the NP/2 disjoint
+// rotations of the round-robin ordering.  Thread (ia, ib) of the first
+// (NP/2)^2 owns the 2x2 block of rows (p_ia, q_ia) and columns (p_ib, q_ib):
+// it reads the block from the current copy of A, writes J_ia^T block J_ib
+// into the other copy (L.W), and rotates the same 2x2 block of V in place
+// by J_ib (every entry of A and V belongs to exactly one block per round),
+// so a round needs one barrier; with NP = 16 the blocks are one wave, whose
+// LDS accesses stay in program order, and the rounds need none.  Every
+// rotation is computed by the same instructions from the same inputs
+// wherever it is used: lane l computes the rotation of pair l mod NP/2 (its
+// own column pair) and, for NP <= 32, its row pair's as well; for NP = 64
+// the row pair's comes from lane ia of the wave by a shuffle.
 //
 // Only the leading `rtop` eigenpairs are wanted, so the stopping test looks
 // at the rows of the rtop largest diagonal entries: it stops when their
-// off-diagonal mass is below 1e-20 of their diagonal mass (an eigenvector
-// error below 1e-10 / relative gap).  Returns the number of sweeps run;
-// *conv tells whether the test passed.
+// off-diagonal mass is below tol2 of their diagonal mass.  Returns the
+// number of sweeps run; *conv tells whether the test passed.  On return
+// L.A holds the rotated matrix; L.W is overwritten.
 template <int NP, int NT>
 __device__ int jacobi_core(JacLds<NP>& L, int n, int rtop, bool* conv, double tol2 = kOffTol2) {
-  constexpr int PAIRS = NP / 2, ROUNDS = NP - 1;
-  const int tid = threadIdx.x;
+  constexpr int PAIRS = NP / 2, ROUNDS = NP - 1, NB = PAIRS * PAIRS, NW = NT / 64;
+  constexpr bool kOneWave = NB == 64, kLocalRows = NP <= 32;
+  static_assert(NB <= NT && NB % 64 == 0 && 64 % PAIRS == 0 && NP <= 64 && NW <= 16,
+                "one thread per 2x2 block, whole waves");
+  static_assert(ROUNDS % 2 == 1, "an odd number of buffer swaps per sweep");
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double (*A)[NP + 1] = L.A;
+  double (*B)[NP + 1] = L.W;
   *conv = false;
   int sweep = 0;
   for (; sweep <= kMaxSweeps; ++sweep) {
-    double off = 0.0, dg = 0.0;
-    if (tid < n) {
-      double dx = L.A[tid][tid];
-      int rank = 0;
-      for (int y = 0; y < n; ++y) {
-        double dy = L.A[y][y];
-        rank += (dy > dx) || (dy == dx && y < tid);
+    // stopping test: wave w takes rows w, w + NW, ...; the rank of a row's
+    // diagonal entry (descending, ties by index) is a ballot over the lanes
+    {
+      const int yl = lane < NP ? lane : 0;
+      const double dy = A[yl][yl];
+      double acc = 0.0, dgs = 0.0;
+      for (int x = w; x < n; x += NW) {
+        const double v = A[x][yl], dx = A[x][x];
+        const unsigned long long m = __ballot(lane < n && (dy > dx || (dy == dx && lane < x)));
+        if (__popcll(m) < (unsigned)rtop) {
+          acc = fma(v, lane < n && lane != x ? v : 0.0, acc);
+          dgs = fma(dx, dx, dgs);
+        }
       }
-      if (rank < rtop) {
-        dg = dx * dx;
-        for (int y = 0; y < n; ++y)
-          if (y != tid) off += L.A[tid][y] * L.A[tid][y];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) {
+        L.red[0][w] = acc;
+        L.red[1][w] = dgs;
       }
     }
-    block_sum2n<NT>(off, dg, L.red);
-    *conv = (off <= tol2 * dg) || dg == 0.0;
+    __syncthreads();
+    if (tid == 0) {
+      double off = 0.0, dg = 0.0;
+      for (int i = 0; i < NW; ++i) {
+        off += L.red[0][i];
+        dg += L.red[1][i];
+      }
+      L.rk[0] = (off <= tol2 * dg) || dg == 0.0;
+    }
+    __syncthreads();
+    *conv = L.rk[0] != 0;
+    __syncthreads();
     if (*conv || sweep == kMaxSweeps) break;
-    for (int r = 0; r < ROUNDS; ++r) {
-      if (tid < PAIRS) {
-        int p, q;
-        jpair_c<NP>(r, tid, &p, &q);
-        double apq = L.A[p][q], app = L.A[p][p], aqq = L.A[q][q];
-        double c = 1.0, sn = 0.0, t = 0.0;
-        if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * (fabs(app) + fabs(aqq))) {
-          double th = (aqq - app) / (2.0 * apq);
-          t = fabs(th) > 1e150 ? 0.5 / th : copysign(1.0, th) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-          c = rsqrt(fma(t, t, 1.0));
-          sn = t * c;
+    // (no barrier inside a branch that can differ between waves)
+    if (!kOneWave || w == 0) {
+      for (int r = 0; r < ROUNDS; ++r) {
+        if (tid < NB) {
+          const int ia = tid / PAIRS, ib = tid % PAIRS;
+          int pa, qa, pb, qb;
+          jpair_c<NP>(r, ia, &pa, &qa);
+          jpair_c<NP>(r, ib, &pb, &qb);
+          // everything this thread reads, before anything is written
+          const double bpp = A[pb][pb], bqq = A[qb][qb], bpq = A[pb][qb];
+          double app = 0.0, aqq = 0.0, apq = 0.0;
+          if (kLocalRows) {
+            app = A[pa][pa];
+            aqq = A[qa][qa];
+            apq = A[pa][qa];
+          }
+          const double w11 = A[pa][pb], w12 = A[pa][qb], w21 = A[qa][pb], w22 = A[qa][qb];
+          const double v11 = L.V[pa][pb], v12 = L.V[pa][qb], v21 = L.V[qa][pb], v22 = L.V[qa][qb];
+          double cb, sb, ca, sa;
+          jacobi_rotation(bpp, bqq, bpq, &cb, &sb);
+          if (kLocalRows) {
+            jacobi_rotation(app, aqq, apq, &ca, &sa);
+          } else {
+            ca = __shfl(cb, ia, 64);
+            sa = __shfl(sb, ia, 64);
+          }
+          const double r11 = ca * w11 - sa * w21, r12 = ca * w12 - sa * w22;
+          const double r21 = sa * w11 + ca * w21, r22 = sa * w12 + ca * w22;
+          B[pa][pb] = cb * r11 - sb * r12;
+          B[pa][qb] = sb * r11 + cb * r12;
+          B[qa][pb] = cb * r21 - sb * r22;
+          B[qa][qb] = sb * r21 + cb * r22;
+          L.V[pa][pb] = cb * v11 - sb * v12;
+          L.V[pa][qb] = sb * v11 + cb * v12;
+          L.V[qa][pb] = cb * v21 - sb * v22;
+          L.V[qa][qb] = sb * v21 + cb * v22;
         }
-        L.rc[tid] = c;
-        L.rs[tid] = sn;
-        L.rt[tid] = t;
+        if (kOneWave) __builtin_amdgcn_wave_barrier();
+        else __syncthreads();
+        double (*T)[NP + 1] = A;
+        A = B;
+        B = T;
       }
-      __syncthreads();
-      for (int blk = tid; blk < PAIRS * PAIRS; blk += NT) {
-        int ia = blk / PAIRS, ib = blk % PAIRS;
-        int pa, qa, pb, qb;
-        jpair_c<NP>(r, ia, &pa, &qa);
-        jpair_c<NP>(r, ib, &pb, &qb);
-        if (ia == ib) {
-          double ta = L.rt[ia], apq = L.A[pa][qa];
-          L.A[pa][pa] -= ta * apq;
-          L.A[qa][qa] += ta * apq;
-          L.A[pa][qa] = 0.0;
-          L.A[qa][pa] = 0.0;
-        } else {
-          double ca = L.rc[ia], sa = L.rs[ia], cb = L.rc[ib], sb = L.rs[ib];
-          double w11 = L.A[pa][pb], w12 = L.A[pa][qb], w21 = L.A[qa][pb], w22 = L.A[qa][qb];
-          double r11 = ca * w11 - sa * w21, r12 = ca * w12 - sa * w22;
-          double r21 = sa * w11 + ca * w21, r22 = sa * w12 + ca * w22;
-          L.A[pa][pb] = cb * r11 - sb * r12;
-          L.A[pa][qb] = sb * r11 + cb * r12;
-          L.A[qa][pb] = cb * r21 - sb * r22;
-          L.A[qa][qb] = sb * r21 + cb * r22;
-        }
-      }
-      for (int it = tid; it < NP * PAIRS; it += NT) {
-        int x = it / PAIRS, ib = it % PAIRS;
-        int pb, qb;
-        jpair_c<NP>(r, ib, &pb, &qb);
-        double cb = L.rc[ib], sb = L.rs[ib];
-        double v1 = L.V[x][pb], v2 = L.V[x][qb];
-        L.V[x][pb] = cb * v1 - sb * v2;
-        L.V[x][qb] = sb * v1 + cb * v2;
-      }
+    }
+    if (kOneWave) {
+      // sweeps 0..sweep done, ROUNDS (odd) swaps each
+      A = (sweep & 1) ? L.A : L.W;
+      B = (sweep & 1) ? L.W : L.A;
       __syncthreads();
     }
+  }
+  // ROUNDS is odd: after an odd number of sweeps the matrix is in L.W
+  if (sweep & 1) {
+    for (int e = tid; e < NP * NP; e += NT) L.A[e / NP][e % NP] = L.W[e / NP][e % NP];
+    __syncthreads();
   }
   return sweep;
 }
