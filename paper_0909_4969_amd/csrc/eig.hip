@@ -545,12 +545,20 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(ReduceArgs a, Status s) {
 //    by Y Y^T, then two Cholesky-QR passes), and again.
 // The Ritz vectors are the factor (sign rule as everywhere); theta are the
 // squared singular values (the Gram's eigenvalues).
+//
+// The same iteration runs on a row-side Gram G = Y_(k) Y_(k)^T of side
+// 33..64 held in LDS (GRAM): one product by G replaces the two by Y, and
+// the start is the current factor (fixed pseudo-random columns only, when
+// there is none: the HOSVD).  It reports through `done` whether the test
+// passed; if not, the caller's Jacobi solve of the same Gram runs instead.
 constexpr int kSsMaxI = 128, kSsMaxK = 64, kSsB = 16, kSsMaxIt = 8;
 
 struct SsArgs {
   const float* Y;          // view (O, I, Q) of Y_k: Y_(k)[i][o Q + q] = Y[(o I + i) Q + q]
+  const double* G;         // GRAM: the I x I Gram, row-major
+  int32_t* done;           // GRAM: set to 1 when the residual test passed, else 0
   uint32_t O, I, Q, K, R;
-  const double* Aprev;     // I x R, the current factor
+  const double* Aprev;     // I x R, the current factor, or null
   double* state;           // I x 16: the block of the last solve
   double* lam;             // >= 16
   int32_t* tag;
@@ -589,7 +597,7 @@ __device__ void ss_mm(const double* A, int lda, const double* Bm, int ldb, doubl
   __syncthreads();
 }
 
-template <int NT>
+template <int NT, bool GRAM>
 __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   if (a.st.skip()) return;
   constexpr int B = kSsB, LB = B + 1, LK = kSsMaxK + 1;
@@ -606,7 +614,13 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   const int Mp = (I + 15) / 16 * 16, Kp = (K + 15) / 16 * 16;
   // eight loads per thread issued before their LDS stores
   static_assert(kSsMaxI * kSsMaxK % (8 * NT) == 0, "Y load in groups of eight");
-  for (int e0 = 0; e0 < kSsMaxI * kSsMaxK; e0 += 8 * NT) {
+  if (GRAM) {   // G (I x I, I <= 64) in the first rows of Y, zero padded
+    for (int e = tid; e < kSsMaxK * kSsMaxK; e += NT) {
+      const int i = e / kSsMaxK, k = e % kSsMaxK;
+      Y[i][k] = (i < I && k < I) ? a.G[(size_t)i * I + k] : 0.0;
+    }
+  }
+  for (int e0 = 0; e0 < (GRAM ? 0 : kSsMaxI * kSsMaxK); e0 += 8 * NT) {
     float v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -633,7 +647,7 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
       v[u] = 0.0;
       if (i < I) {
         if (warm) v[u] = a.state[i * B + j];
-        else if (j < R) v[u] = a.Aprev[(size_t)i * R + j];
+        else if (j < R && a.Aprev) v[u] = a.Aprev[(size_t)i * R + j];
         else {
           uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(j + 1) * 0x85EBCA77u;
           h ^= h >> 15;
@@ -692,10 +706,14 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
       __syncthreads();
     }
   };
-  // D = Y (Y^T P)
+  // D = Y (Y^T P), or D = G P
   auto gq = [&](double (*P)[LB], double (*D)[LB]) __attribute__((always_inline)) {
-    ss_mm<NT, true>(&Y[0][0], LK, &P[0][0], LB, &W[0][0], LB, Kp, B, Mp);
-    ss_mm<NT, false>(&Y[0][0], LK, &W[0][0], LB, &D[0][0], LB, Mp, B, Kp);
+    if (GRAM) {
+      ss_mm<NT, false>(&Y[0][0], LK, &P[0][0], LB, &D[0][0], LB, Mp, B, Mp);
+    } else {
+      ss_mm<NT, true>(&Y[0][0], LK, &P[0][0], LB, &W[0][0], LB, Kp, B, Mp);
+      ss_mm<NT, false>(&Y[0][0], LK, &W[0][0], LB, &D[0][0], LB, Mp, B, Kp);
+    }
   };
   // degree-2 Chebyshev filter on [0, tau] applied to the block Qc, then two
   // Cholesky-QR passes (plain steps if tau is not a usable bound)
@@ -796,6 +814,13 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
     filter(th[B - 1], ref);
     filter(th[B - 1], ref);
   }
+  // GRAM: a block that did not pass the test is dropped (the Jacobi solve
+  // of the caller runs instead and leaves its own warm-start tag)
+  if (GRAM) {
+    const bool ok = conv || worst <= 1e-8 * ref;
+    if (tid == 0) *a.done = ok ? 1 : 0;
+    if (!ok) return;
+  }
   // sign rule and stores; the block is kept for the next solve
   if (tid < R) {
     double best = -1.0, val = 0.0;
@@ -820,8 +845,10 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   if (tid == 0) {
     *a.tag = a.tagval;
     if (a.stats) *a.stats = 3000 + it + 1;
-    if (!conv && worst > 1e-8 * ref) atomicCAS(a.st.st, 0, MACH_ENOCONV);
-    if (!(th[R - 1] > 1e-13 * th[0])) atomicCAS(a.st.st, 0, MACH_EDEGENERATE);
+    if (!GRAM) {
+      if (!conv && worst > 1e-8 * ref) atomicCAS(a.st.st, 0, MACH_ENOCONV);
+      if (!(th[R - 1] > 1e-13 * th[0])) atomicCAS(a.st.st, 0, MACH_EDEGENERATE);
+    }
   }
 }
 
@@ -2040,7 +2067,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     a.af = (float*)(ws + SL.af[k]);
     a.stats = (int32_t*)(ws + SL.status + 96) + k;
     a.st = c.stat();
-    hipLaunchKernelGGL((k_mode_ss<256>), dim3(1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_mode_ss<256, false>), dim3(1), dim3(256), 0, st, a);
     return hipGetLastError();
   }
   if (m.s <= (uint32_t)kSmallEig) {
@@ -2112,6 +2139,28 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     a.af = (float*)(ws + SL.af[k]);
     a.stats = (int32_t*)(ws + SL.status + 96) + k;
     a.st = c.stat();
+    // Row-side Gram of side 33..64 and R <= 12: block iteration on the Gram
+    // first (its own warm-start tag); the Jacobi solve runs, cold, only
+    // when that did not pass its test.
+    if (!m.kside && m.s > 32 && m.s <= (uint32_t)kSsMaxK && m.R <= 12) {
+      SsArgs g{};
+      g.G = a.part;
+      g.done = c.tags() + kTagDone;
+      g.I = m.I;
+      g.K = m.I;
+      g.R = m.R;
+      g.Aprev = A_out;
+      g.state = c.d(m.V);
+      g.lam = c.d(m.lam);
+      g.tag = c.tags() + k;
+      g.tagval = (tagval & 0x00ffffff) | 0x4e000000;
+      g.Aout = A_out;
+      g.af = (float*)(ws + SL.af[k]);
+      g.stats = a.stats;
+      g.st = c.stat();
+      hipLaunchKernelGGL((k_mode_ss<256, true>), dim3(1), dim3(256), 0, st, g);
+      a.st = c.stat(true);
+    }
     if (m.s <= 16)
       hipLaunchKernelGGL((k_mode_solve<16, 256>), dim3(1), dim3(256), 0, st, a);
     else if (m.s <= 32)

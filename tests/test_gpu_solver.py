@@ -44,17 +44,27 @@ def _col216():
 def _col100():
     X, _ = synth.workload1(shape=(600, 12, 12), ranks=(10, 10, 10), seed=17)
     return X.astype(np.float32), (10, 10, 10), 0.3, 18
+def _row48():
+    X, _ = synth.workload1(shape=(48, 12, 12), ranks=(6, 10, 10), seed=19)
+    return X.astype(np.float32), (6, 10, 10), 0.3, 20
+def _row64r12():
+    X, _ = synth.workload1(shape=(64, 12, 12), ranks=(12, 10, 10), seed=21)
+    return X.astype(np.float32), (12, 10, 10), 0.3, 22
 
 # monitor-128x16x2048: mode 0 has I = 128 > K = 64 with R = 8, the column-side
 # block subspace iteration on Y Y^T.  Sweep Grams with a side above 64 (the
 # block subspace iteration of the sweep): rowside96 (mode 0, I = 96 < K =
 # 100, row side), colside216 (mode 3, K = 216 < I = 256, column side with
-# back-projection), colside100 (mode 0, K = 100 < I = 600).
+# back-projection), colside100 (mode 0, K = 100 < I = 600).  Row-side
+# Grams of side 33..64 with R <= 12 (block iteration on the Gram, Jacobi when
+# it does not pass its test): rowside48 (mode 0, R = 6), rowside64r12 (mode
+# 0, R = 12, four columns of guard in the block of 16).
 CASES = {"tucker-64x32x48-f64": _w1, "monitor-32x16x2048": _w2, "monitor-128x16x2048": _w2s,
          "monitor-p0.01-64x16x4096": _w2p01,
          "voxel-16x16x16x64": _w3, "matrix-300x200": _mat, "sides>64-96x80x6": _big_side,
          "rowside96-96x12x12": _row96, "colside216-16x16x16x256": _col216,
-         "colside100-600x12x12": _col100}
+         "colside100-600x12x12": _col100, "rowside48-48x12x12": _row48,
+         "rowside64r12-64x12x12": _row64r12}
 
 # Core and error bars.  The float32 bar is 1e-5 relative (norm-wise) on the
 # core, so 2e-5 relative on its squared norm (d||G||^2 / ||G||^2 = 2 d||G|| /
@@ -116,6 +126,11 @@ def test_sweeps_one_step_and_end_to_end(name):
             used = M.solver_stats(dec.solver)["jacobi_sweeps"][0]
             say(f"  sweep {it} mode 0: block iteration, {used - 3000} Rayleigh-Ritz rounds")
             assert 3000 < used <= 3008, used
+        if name.startswith("rowside48") or name.startswith("rowside64"):
+            from paper_0909_4969_amd import mach as M
+            used = M.solver_stats(dec.solver)["jacobi_sweeps"][0]
+            say(f"  sweep {it} mode 0: " + (f"block iteration on the Gram, {used - 3000} Rayleigh-Ritz rounds"
+                                            if used > 3000 else f"Jacobi, {used % 1000} sweeps"))
         sing = {}
         A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_ref, ranks, sing=sing)
         for n in range(len(ranks)):
