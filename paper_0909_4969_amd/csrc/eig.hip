@@ -546,17 +546,20 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(ReduceArgs a, Status s) {
 // The Ritz vectors are the factor (sign rule as everywhere); theta are the
 // squared singular values (the Gram's eigenvalues).
 //
-// The same iteration runs on a row-side Gram G = Y_(k) Y_(k)^T of side
-// 33..64 held in LDS (GRAM): one product by G replaces the two by Y, and
-// the start is the current factor (fixed pseudo-random columns only, when
-// there is none: the HOSVD).  It reports through `done` whether the test
-// passed; if not, the caller's Jacobi solve of the same Gram runs instead.
-constexpr int kSsMaxI = 128, kSsMaxK = 64, kSsB = 16, kSsMaxIt = 8;
+// The same iteration runs on a row-side Gram G = Y_(k) Y_(k)^T, one product
+// by G in place of the two by Y, with the current factor as the cold start
+// (fixed pseudo-random columns only, when there is none: the HOSVD):
+//  - OP 1, side 33..64: G in LDS; it reports through `done` whether the
+//    test passed, and if not, the caller's Jacobi solve of the same Gram
+//    runs instead;
+//  - OP 2, side 80..256 (a multiple of 16): G read from global memory (it
+//    stays in L2 across the products), up to 16 Rayleigh-Ritz steps.
+constexpr int kSsMaxI = 128, kSsMaxK = 64, kSsB = 16, kSsMaxIt = 8, kSsMaxIG = 256;
 
 struct SsArgs {
-  const float* Y;          // view (O, I, Q) of Y_k: Y_(k)[i][o Q + q] = Y[(o I + i) Q + q]
-  const double* G;         // GRAM: the I x I Gram, row-major
-  int32_t* done;           // GRAM: set to 1 when the residual test passed, else 0
+  const float* Y;          // OP 0: view (O, I, Q) of Y_k: Y_(k)[i][o Q + q] = Y[(o I + i) Q + q]
+  const double* G;         // OP 1, 2: the I x I Gram, row-major
+  int32_t* done;           // OP 1: set to 1 when the residual test passed, else 0
   uint32_t O, I, Q, K, R;
   const double* Aprev;     // I x R, the current factor, or null
   double* state;           // I x 16: the block of the last solve
@@ -578,32 +581,79 @@ __device__ void ss_mm(const double* A, int lda, const double* Bm, int ldb, doubl
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
   const int tn = N / 16, nt = (M / 16) * tn;
+  for (int t0 = w; t0 < nt; t0 += 2 * NW) {
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int t = w + u * NW;
-    if (t < nt) {
-      const int ti = t / tn, tj = t % tn;
-      v4d c = {0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < Kd; k0 += 4) {
-        const int k = k0 + lk, row = ti * 16 + li;
-        const double av = TA ? A[k * lda + row] : A[row * lda + k];
-        const double bv = Bm[k * ldb + tj * 16 + li];
-        c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+    for (int u = 0; u < 2; ++u) {
+      const int t = t0 + u * NW;
+      if (t < nt) {
+        const int ti = t / tn, tj = t % tn;
+        v4d c = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < Kd; k0 += 4) {
+          const int k = k0 + lk, row = ti * 16 + li;
+          const double av = TA ? A[k * lda + row] : A[row * lda + k];
+          const double bv = Bm[k * ldb + tj * 16 + li];
+          c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) D[(ti * 16 + lk + 4 * v) * ldd + tj * 16 + li] = c[v];
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) D[(ti * 16 + lk + 4 * v) * ldd + tj * 16 + li] = c[v];
     }
   }
   __syncthreads();
 }
 
-template <int NT, bool GRAM>
+// D (M x 16, LDS) = A B for A in global memory (M x Kd, row-major, lda) and
+// B in LDS (Kd x 16); M and Kd multiples of 16.  Each wave takes two 16-row
+// tiles at a time; their A entries are requested 16 summation steps at a
+// time, before the products that use them.
+template <int NT>
+__device__ void ss_mm_ga(const double* __restrict__ A, int lda, const double* Bm, int ldb, double* D,
+                         int ldd, int M, int Kd) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const int nt = M / 16;
+  for (int t0 = w; t0 < nt; t0 += 2 * NW) {
+    const int t1 = t0 + NW;
+    const bool two = t1 < nt;
+    const double* r0 = A + (size_t)(t0 * 16 + li) * lda + lk;
+    const double* r1 = A + (size_t)((two ? t1 : t0) * 16 + li) * lda + lk;
+    v4d c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < Kd; k0 += 64) {
+      double a0[16], a1[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const bool in = k0 + 4 * u < Kd;
+        a0[u] = in ? r0[k0 + 4 * u] : 0.0;
+        a1[u] = in ? r1[k0 + 4 * u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        if (k0 + 4 * u < Kd) {
+          const double bv = Bm[(k0 + 4 * u + lk) * ldb + li];
+          c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv, c1, 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      D[(t0 * 16 + lk + 4 * v) * ldd + li] = c0[v];
+      if (two) D[(t1 * 16 + lk + 4 * v) * ldd + li] = c1[v];
+    }
+  }
+  __syncthreads();
+}
+
+template <int NT, int OP>
 __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
+  constexpr bool GRAM = OP != 0;
+  constexpr int MAXI = OP == 2 ? kSsMaxIG : kSsMaxI, MAXIT = OP == 2 ? 16 : kSsMaxIt;
   if (a.st.skip()) return;
   constexpr int B = kSsB, LB = B + 1, LK = kSsMaxK + 1;
-  __shared__ double Y[kSsMaxI][LK];
-  __shared__ double Q0[kSsMaxI][LB], Q1[kSsMaxI][LB], Q2[kSsMaxI][LB];
-  __shared__ double W[kSsMaxK][LB];
+  // Y (OP 0), G (OP 1); nothing for OP 2
+  __shared__ double Y[OP == 0 ? kSsMaxI : (OP == 1 ? kSsMaxK : 1)][LK];
+  __shared__ double Q0[MAXI][LB], Q1[MAXI][LB], Q2[MAXI][LB];
+  __shared__ double W[OP == 0 ? kSsMaxK : 1][LB];
   __shared__ double S[B][LB];
   __shared__ double th[B], rinv[B], sgn[B];
   __shared__ double red[NT / 16][B];
@@ -614,7 +664,7 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   const int Mp = (I + 15) / 16 * 16, Kp = (K + 15) / 16 * 16;
   // eight loads per thread issued before their LDS stores
   static_assert(kSsMaxI * kSsMaxK % (8 * NT) == 0, "Y load in groups of eight");
-  if (GRAM) {   // G (I x I, I <= 64) in the first rows of Y, zero padded
+  if (OP == 1) {   // G (I x I, I <= 64) in Y, zero padded
     for (int e = tid; e < kSsMaxK * kSsMaxK; e += NT) {
       const int i = e / kSsMaxK, k = e % kSsMaxK;
       Y[i][k] = (i < I && k < I) ? a.G[(size_t)i * I + k] : 0.0;
@@ -638,12 +688,12 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
     }
   }
   const bool warm = *a.tag == a.tagval;
-  static_assert(kSsMaxI * B == 8 * NT, "start block loaded as eight values per thread");
-  {
+  static_assert(MAXI * B % (8 * NT) == 0, "start block loaded eight values per thread at a time");
+  for (int e0 = 0; e0 < MAXI * B; e0 += 8 * NT) {
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = u * NT + tid, i = e / B, j = e % B;
+      const int e = e0 + u * NT + tid, i = e / B, j = e % B;
       v[u] = 0.0;
       if (i < I) {
         if (warm) v[u] = a.state[i * B + j];
@@ -659,7 +709,7 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = u * NT + tid;
+      const int e = e0 + u * NT + tid;
       Q0[e / B][e % B] = v[u];
     }
   }
@@ -708,7 +758,9 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   };
   // D = Y (Y^T P), or D = G P
   auto gq = [&](double (*P)[LB], double (*D)[LB]) __attribute__((always_inline)) {
-    if (GRAM) {
+    if (OP == 2) {
+      ss_mm_ga<NT>(a.G, I, &P[0][0], LB, &D[0][0], LB, Mp, Mp);
+    } else if (OP == 1) {
       ss_mm<NT, false>(&Y[0][0], LK, &P[0][0], LB, &D[0][0], LB, Mp, B, Mp);
     } else {
       ss_mm<NT, true>(&Y[0][0], LK, &P[0][0], LB, &W[0][0], LB, Kp, B, Mp);
@@ -808,15 +860,15 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
       Zb = t;
     }
     conv = worst <= 1e-10 * ref;
-    if (conv || it == kSsMaxIt - 1) break;
+    if (conv || it == MAXIT - 1) break;
     // tau = theta_16; two applications between Rayleigh-Ritz steps (one
     // seldom sufficed, and the step between would not change the span)
     filter(th[B - 1], ref);
     filter(th[B - 1], ref);
   }
-  // GRAM: a block that did not pass the test is dropped (the Jacobi solve
+  // OP 1: a block that did not pass the test is dropped (the Jacobi solve
   // of the caller runs instead and leaves its own warm-start tag)
-  if (GRAM) {
+  if (OP == 1) {
     const bool ok = conv || worst <= 1e-8 * ref;
     if (tid == 0) *a.done = ok ? 1 : 0;
     if (!ok) return;
@@ -845,10 +897,8 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   if (tid == 0) {
     *a.tag = a.tagval;
     if (a.stats) *a.stats = 3000 + it + 1;
-    if (!GRAM) {
-      if (!conv && worst > 1e-8 * ref) atomicCAS(a.st.st, 0, MACH_ENOCONV);
-      if (!(th[R - 1] > 1e-13 * th[0])) atomicCAS(a.st.st, 0, MACH_EDEGENERATE);
-    }
+    if (OP != 1 && !conv && worst > 1e-8 * ref) atomicCAS(a.st.st, 0, MACH_ENOCONV);
+    if (OP == 0 && !(th[R - 1] > 1e-13 * th[0])) atomicCAS(a.st.st, 0, MACH_EDEGENERATE);
   }
 }
 
@@ -2067,7 +2117,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     a.af = (float*)(ws + SL.af[k]);
     a.stats = (int32_t*)(ws + SL.status + 96) + k;
     a.st = c.stat();
-    hipLaunchKernelGGL((k_mode_ss<256, false>), dim3(1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_mode_ss<256, 0>), dim3(1), dim3(256), 0, st, a);
     return hipGetLastError();
   }
   if (m.s <= (uint32_t)kSmallEig) {
@@ -2158,7 +2208,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
       g.af = (float*)(ws + SL.af[k]);
       g.stats = a.stats;
       g.st = c.stat();
-      hipLaunchKernelGGL((k_mode_ss<256, true>), dim3(1), dim3(256), 0, st, g);
+      hipLaunchKernelGGL((k_mode_ss<256, 1>), dim3(1), dim3(256), 0, st, g);
       a.st = c.stat(true);
     }
     if (m.s <= 16)
@@ -2194,6 +2244,26 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
   }
   hipError_t e = launch_gram_y(SL, ws, k, prec, hdr, st);
   if (e != hipSuccess) return e;
+  // Row-side Gram of side 80..256 (a multiple of 16) and R <= 12: block
+  // iteration with G read from global memory.
+  if (!m.kside && m.s <= (uint32_t)kSsMaxIG && m.s % 16 == 0 && m.R <= 12) {
+    SsArgs g{};
+    g.G = c.d(SL.G);
+    g.I = m.I;
+    g.K = m.I;
+    g.R = m.R;
+    g.Aprev = A_out;
+    g.state = c.d(m.Q64);
+    g.lam = c.d(m.lam);
+    g.tag = c.tags() + k;
+    g.tagval = (tagval & 0x00ffffff) | 0x4e000000;
+    g.Aout = A_out;
+    g.af = (float*)(ws + SL.af[k]);
+    g.stats = (int32_t*)(ws + SL.status + 96) + k;
+    g.st = c.stat();
+    hipLaunchKernelGGL((k_mode_ss<256, 2>), dim3(1), dim3(256), 0, st, g);
+    return hipGetLastError();
+  }
   const double* G = c.d(SL.G);
   double* V = c.d(m.Q64);
   const uint32_t ldv = kBlock;
