@@ -573,8 +573,10 @@ struct SsArgs {
 };
 
 // D (M x N) = op(A) B on float64 MFMA for LDS arrays with leading dims:
-// op(A)[i][k] = TA ? A[k][i] : A[i][k]; M, N multiples of 16, Kd of 4, at
-// most 2 output tiles per wave.  D must not alias A or B.
+// op(A)[i][k] = TA ? A[k][i] : A[i][k]; M, N and Kd multiples of 16.  Each
+// wave takes 16 x 16 output tiles, two at a time; the operands of four
+// summation steps are read from LDS before their products.  D must not
+// alias A or B.
 template <int NT, bool TA>
 __device__ void ss_mm(const double* A, int lda, const double* Bm, int ldb, double* D, int ldd, int M,
                       int N, int Kd) {
@@ -582,21 +584,31 @@ __device__ void ss_mm(const double* A, int lda, const double* Bm, int ldb, doubl
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
   const int tn = N / 16, nt = (M / 16) * tn;
   for (int t0 = w; t0 < nt; t0 += 2 * NW) {
+    const int t1 = t0 + NW;
+    const bool two = t1 < nt;
+    const int ti0 = t0 / tn, tj0 = t0 % tn, ti1 = (two ? t1 : t0) / tn, tj1 = (two ? t1 : t0) % tn;
+    const int row0 = ti0 * 16 + li, row1 = ti1 * 16 + li, col0 = tj0 * 16 + li, col1 = tj1 * 16 + li;
+    v4d c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < Kd; k0 += 16) {
+      double a0[4], a1[4], b0[4], b1[4];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = t0 + u * NW;
-      if (t < nt) {
-        const int ti = t / tn, tj = t % tn;
-        v4d c = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < Kd; k0 += 4) {
-          const int k = k0 + lk, row = ti * 16 + li;
-          const double av = TA ? A[k * lda + row] : A[row * lda + k];
-          const double bv = Bm[k * ldb + tj * 16 + li];
-          c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) D[(ti * 16 + lk + 4 * v) * ldd + tj * 16 + li] = c[v];
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * u + lk;
+        a0[u] = TA ? A[k * lda + row0] : A[row0 * lda + k];
+        a1[u] = TA ? A[k * lda + row1] : A[row1 * lda + k];
+        b0[u] = Bm[k * ldb + col0];
+        b1[u] = Bm[k * ldb + col1];
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], c1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      D[(ti0 * 16 + lk + 4 * v) * ldd + col0] = c0[v];
+      if (two) D[(ti1 * 16 + lk + 4 * v) * ldd + col1] = c1[v];
     }
   }
   __syncthreads();
@@ -604,36 +616,53 @@ __device__ void ss_mm(const double* A, int lda, const double* Bm, int ldb, doubl
 
 // D (M x 16, LDS) = A B for A in global memory (M x Kd, row-major, lda) and
 // B in LDS (Kd x 16); M and Kd multiples of 16.  Each wave takes two 16-row
-// tiles at a time; their A entries are requested 16 summation steps at a
-// time, before the products that use them.
+// tiles at a time and walks the summation index in chunks of 32 with two
+// register sets: the A entries of the next chunk are requested from memory
+// while the products of the current one run (B entries are read from LDS
+// just before their products); a last half chunk of 16 is read directly.
 template <int NT>
 __device__ void ss_mm_ga(const double* __restrict__ A, int lda, const double* Bm, int ldb, double* D,
                          int ldd, int M, int Kd) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
-  const int nt = M / 16;
+  const int nt = M / 16, nc = Kd / 32;
   for (int t0 = w; t0 < nt; t0 += 2 * NW) {
     const int t1 = t0 + NW;
     const bool two = t1 < nt;
     const double* r0 = A + (size_t)(t0 * 16 + li) * lda + lk;
     const double* r1 = A + (size_t)((two ? t1 : t0) * 16 + li) * lda + lk;
     v4d c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < Kd; k0 += 64) {
-      double a0[16], a1[16];
+    double x0[8], x1[8], y0[8], y1[8];
+    auto load = [&](double* d0, double* d1, int k0) __attribute__((always_inline)) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const bool in = k0 + 4 * u < Kd;
-        a0[u] = in ? r0[k0 + 4 * u] : 0.0;
-        a1[u] = in ? r1[k0 + 4 * u] : 0.0;
+      for (int u = 0; u < 8; ++u) {
+        d0[u] = r0[k0 + 4 * u];
+        d1[u] = r1[k0 + 4 * u];
       }
+    };
+    auto mul = [&](const double* s0, const double* s1, int k0) __attribute__((always_inline)) {
+      double b[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        if (k0 + 4 * u < Kd) {
-          const double bv = Bm[(k0 + 4 * u + lk) * ldb + li];
-          c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv, c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv, c1, 0, 0, 0);
-        }
+      for (int u = 0; u < 8; ++u) b[u] = Bm[(k0 + 4 * u + lk) * ldb + li];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[u], b[u], c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[u], b[u], c1, 0, 0, 0);
       }
+    };
+    int c = 0;
+    if (nc > 0) load(x0, x1, 0);
+    for (; c + 1 < nc; c += 2) {
+      load(y0, y1, (c + 1) * 32);
+      mul(x0, x1, c * 32);
+      load(x0, x1, (c + 2 < nc ? c + 2 : c + 1) * 32);
+      mul(y0, y1, (c + 1) * 32);
+    }
+    if (c < nc) mul(x0, x1, c * 32);
+    for (int k0 = nc * 32; k0 < Kd; k0 += 4) {   // the half chunk
+      const double bv = Bm[(k0 + lk) * ldb + li];
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(r0[k0], bv, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(r1[k0], bv, c1, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
