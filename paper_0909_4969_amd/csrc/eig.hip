@@ -614,30 +614,33 @@ __device__ void ss_mm(const double* A, int lda, const double* Bm, int ldb, doubl
   __syncthreads();
 }
 
-// D (M x 16, LDS) = A B for A in global memory (M x Kd, row-major, lda) and
-// B in LDS (Kd x 16); M and Kd multiples of 16.  Each wave takes two 16-row
-// tiles at a time and walks the summation index in chunks of 32 with two
-// register sets: the A entries of the next chunk are requested from memory
-// while the products of the current one run (B entries are read from LDS
-// just before their products); a last half chunk of 16 is read directly.
+// D (M x 16, LDS) = A^T B for A in global memory (Kd x M, row-major, lda;
+// the callers' A is symmetric, so this is A B) and B in LDS (Kd x 16); M and
+// Kd multiples of 16.  A lane group reads 16 consecutive entries of a row
+// of A, whole cache lines.  Each wave takes two 16-column tiles at a time
+// and walks the summation index in chunks of 32 with two register sets: the
+// A entries of the next chunk are requested from memory while the products
+// of the current one run (B entries are read from LDS just before their
+// products); a last half chunk of 16 is read directly.
 template <int NT>
 __device__ void ss_mm_ga(const double* __restrict__ A, int lda, const double* Bm, int ldb, double* D,
                          int ldd, int M, int Kd) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
   const int nt = M / 16, nc = Kd / 32;
+  const size_t step = (size_t)4 * lda;   // four summation indices
   for (int t0 = w; t0 < nt; t0 += 2 * NW) {
     const int t1 = t0 + NW;
     const bool two = t1 < nt;
-    const double* r0 = A + (size_t)(t0 * 16 + li) * lda + lk;
-    const double* r1 = A + (size_t)((two ? t1 : t0) * 16 + li) * lda + lk;
+    const double* r0 = A + (size_t)lk * lda + t0 * 16 + li;
+    const double* r1 = A + (size_t)lk * lda + (two ? t1 : t0) * 16 + li;
     v4d c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
     double x0[8], x1[8], y0[8], y1[8];
     auto load = [&](double* d0, double* d1, int k0) __attribute__((always_inline)) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        d0[u] = r0[k0 + 4 * u];
-        d1[u] = r1[k0 + 4 * u];
+        d0[u] = r0[(size_t)(k0 / 4 + u) * step];
+        d1[u] = r1[(size_t)(k0 / 4 + u) * step];
       }
     };
     auto mul = [&](const double* s0, const double* s1, int k0) __attribute__((always_inline)) {
@@ -661,8 +664,8 @@ __device__ void ss_mm_ga(const double* __restrict__ A, int lda, const double* Bm
     if (c < nc) mul(x0, x1, c * 32);
     for (int k0 = nc * 32; k0 < Kd; k0 += 4) {   // the half chunk
       const double bv = Bm[(k0 + lk) * ldb + li];
-      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(r0[k0], bv, c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(r1[k0], bv, c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(r0[(size_t)(k0 / 4) * step], bv, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(r1[(size_t)(k0 / 4) * step], bv, c1, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
