@@ -2329,6 +2329,26 @@ hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const So
   uint32_t ldv;
   int32_t* tagc = c.tags() + kTagCold;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, tagc, 0);
+  // Row-side Gram of side 80..256 (a multiple of 16) and R <= 12: block
+  // subspace iteration from fixed pseudo-random columns, G read from L2.
+  if (!SL.hosvd_kside[n] && s > (uint32_t)kSmallEig && s <= (uint32_t)kSsMaxIG && s % 16 == 0 && R <= 12) {
+    SsArgs g{};
+    g.G = G;
+    g.I = s;
+    g.K = s;
+    g.R = (uint32_t)R;
+    g.Aprev = nullptr;
+    g.state = c.d(SL.Aw);
+    g.lam = lam;
+    g.tag = tagc;
+    g.tagval = 0x4f000000 | (int32_t)s;
+    g.Aout = A_out;
+    g.af = (float*)(ws + SL.af[n]);
+    g.stats = (int32_t*)(ws + SL.status + 128) + n;
+    g.st = c.stat();
+    hipLaunchKernelGGL((k_mode_ss<256, 2>), dim3(1), dim3(256), 0, st, g);
+    return hipGetLastError();
+  }
   if (s <= (uint32_t)kSmallEig) {
     ldv = s;
     jacobi(c, G, 1, s, V, lam, tagc, 0x48000000 | (int32_t)s, false, R);
