@@ -1868,10 +1868,13 @@ __global__ __launch_bounds__(256) void k_norm2(const double* __restrict__ G, uin
   if (threadIdx.x == 0) *out = a;
 }
 
+// Clears the status word, the warm-start tags and the per-mode solve
+// statistics (status words 24..39: sweep solves, then HOSVD solves).
 __global__ void k_solver_init(int32_t* st, int32_t* tags, int ntags) {
   int t = threadIdx.x;
   if (t == 0) *st = 0;
   if (t < ntags) tags[t] = 0;
+  if (t < 16) st[24 + t] = 0;
 }
 
 }  // namespace

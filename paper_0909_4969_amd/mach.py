@@ -268,11 +268,14 @@ def hosvd(sw: SampleWorkspace, ranks, solver: torch.Tensor, factors=None, stream
 
 
 def solver_stats(solver: torch.Tensor):
-    """Diagnostics kept in the solver workspace (synchronises): per mode,
-    the Jacobi sweeps of its last eigensolve (+1000 when warm-started; 3000 +
-    the Rayleigh-Ritz rounds when the column-side block iteration on Y Y^T
-    ran instead) and the subspace-iteration steps of its HOSVD eigensolve
-    (+10000 when the residual tolerance was not reached)."""
+    """Diagnostics kept in the solver workspace (synchronises), cleared by
+    each HOSVD.  Per mode, for its last sweep eigensolve: the Jacobi sweeps
+    (+1000 when warm-started, +2000 when warm-started in the rotated
+    column-side basis), 3000 + the Rayleigh-Ritz rounds of a block subspace
+    iteration (on Y Y^T or on the Gram), or the steps of the subspace
+    iteration of a larger Gram (+10000 when the residual tolerance was not
+    reached); and for its HOSVD eigensolve the same codes of the block or
+    subspace iteration, 0 after a Jacobi solve."""
     raw = solver[96:160].view(torch.int32).cpu().tolist()
     return {"jacobi_sweeps": raw[:8], "hosvd_subspace_steps": raw[8:16]}
 
