@@ -1950,6 +1950,23 @@ void jacobi(const Ctx& c, const double* G, uint32_t nchunk, uint32_t n, double* 
 // Cholesky-QR of X (M x n, ld kBlock): `passes` passes (the first shifted
 // by 1e-15 tr(S) / n), alternating between X and the scratch Y.  Returns
 // the buffer holding the result (X after an even number of passes).
+// The n x n partials (chunk-minor, nchunk chunks) summed into one copy in
+// the reduction scratch, one wave per entry, so that the single-workgroup
+// kernel after it reads n^2 values instead of n^2 nchunk.
+const double* reduce_square(const Ctx& c, const double* part, uint32_t nchunk, uint32_t n,
+                            Status sd) {
+  ReduceArgs r{};
+  r.in = part;
+  r.out = c.d(c.SL->sred) + kSredGram;
+  r.nent = n * n;
+  r.gsize = r.nent;
+  r.es = nchunk;
+  r.cs = 1;
+  r.nch[0] = nchunk;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3(cdiv(r.nent, 4)), dim3(256), 0, c.st, r, sd);
+  return r.out;
+}
+
 double* orthonormalise(const Ctx& c, double* X, double* Y, uint32_t M, uint32_t n, int passes,
                        bool with_done) {
   Status sd = c.stat(with_done);
@@ -1963,8 +1980,9 @@ double* orthonormalise(const Ctx& c, double* X, double* Y, uint32_t M, uint32_t 
   for (int pass = 0; pass < passes; ++pass) {
     hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, src, kBlock, src, kBlock, M, n,
                        rows, c.d(c.SL->part), sd);
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, c.st, c.d(c.SL->part), nchunk, n,
-                       pass == 0 ? 1e-15 : 0.0, B, sd);
+    const double* S = nchunk > 1 ? reduce_square(c, c.d(c.SL->part), nchunk, n, sd) : c.d(c.SL->part);
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, c.st, S, 1u, n, pass == 0 ? 1e-15 : 0.0, B,
+                       sd);
     gemm(c, src, kBlock, B, n, dst, kBlock, M, n, n, with_done);
     double* t = src;
     src = dst;
@@ -2039,10 +2057,11 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
     nchunk = cdiv(s, rows);
     hipLaunchKernelGGL(k_atb_partial, dim3(nchunk), dim3(256), 0, c.st, z, kBlock, w, kBlock, s, b, rows,
                        H, sd);
+    const double* Hs = nchunk > 1 ? reduce_square(c, H, nchunk, b, sd) : H;
     // The block is the previous Ritz vectors times G^8, orthonormalised in
     // column order, so H is close to diagonal as it stands: start from the
     // identity (the previous step's rotation would undo that).
-    jacobi(c, H, nchunk, b, VH, lamH, tags + kTagRR, 0, true, (int)R, 1e-24);
+    jacobi(c, Hs, 1, b, VH, lamH, tags + kTagRR, 0, true, (int)R, 1e-24);
     double* zr = other(z, w);
     gemm(c, z, kBlock, VH, b, Qr, kBlock, s, b, b, true);
     gemm(c, w, kBlock, VH, b, zr, kBlock, s, b, b, true);
