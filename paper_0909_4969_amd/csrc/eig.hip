@@ -1345,24 +1345,29 @@ __device__ __forceinline__ void cheb_coef(const Cheb& ch, double* al, double* be
   }
 }
 
-// C[M x N] partials of A[M x K] * B[K x N] (row-major, N <= 64) for long K:
+// C[M x N] partials of A[M x K] * B[K x N] (row-major, N <= NC) for long K:
 // workgroup (x, y) owns rows 64x..64x+63 and the summation slice
 // [y * kSplitK, (y + 1) * kSplitK) (a single slice covers all of K);
-// P[y][m][0..63] (columns >= N are 0).  Tiles of 32 summation indices are staged in LDS (A transposed); each
-// thread accumulates a 4 x 4 block in float64.
+// P[y][m][0..63] (columns >= N are 0).  Tiles of 32 summation indices are
+// staged in LDS (A transposed); each thread accumulates a block of
+// 64 / (256 / (NC / 4)) rows x 4 columns in float64 (4 x 4 for NC = 64,
+// 2 x 4 for NC = 32).
+template <int NC>
 __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ A, uint32_t lda,
                                                      const double* __restrict__ B, uint32_t ldb,
                                                      double* __restrict__ P, uint32_t M, uint32_t K,
                                                      uint32_t N, Cheb ch, Status s) {
+  constexpr int TXN = NC / 4, TYN = 256 / TXN, TR = 64 / TYN;
+  static_assert(TXN * TYN == 256 && TR * TYN == 64, "tile shape");
   if (s.skip()) return;
   __shared__ double As[32][68];
   __shared__ double Bs[32][68];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, tx = tid % TXN, ty = tid / TXN;
   const uint32_t m0 = blockIdx.x * 64, k0 = blockIdx.y * kSplitK;
   const uint32_t k1 = gridDim.y == 1 ? K : min(K, k0 + kSplitK);
-  double acc[4][4];
+  double acc[TR][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TR; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   for (uint32_t kc = k0; kc < k1; kc += 32) {
@@ -1385,14 +1390,13 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ 
     __syncthreads();
 #pragma unroll 8
     for (int kk = 0; kk < 32; ++kk) {
-      double a[4], b[4];
+      double a[TR], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = As[kk][ty * 4 + i];
-        b[i] = Bs[kk][tx * 4 + i];
-      }
+      for (int i = 0; i < TR; ++i) a[i] = As[kk][ty * TR + i];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < TR; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
@@ -1401,9 +1405,14 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ 
   double* o = P + ((size_t)blockIdx.y * M + m0) * 64;
   double al = 1.0, be = 0.0, ga = 0.0;
   if (gridDim.y == 1) cheb_coef(ch, &al, &be, &ga);   // single slice: P is the output
+  if (NC < 64)   // the columns this variant does not compute
+    for (int e = tid; e < 64 * (64 - NC); e += 256) {
+      const uint32_t r = e / (64 - NC), cidx = NC + e % (64 - NC);
+      if (m0 + r < M) o[(size_t)r * 64 + cidx] = 0.0;
+    }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const uint32_t r = ty * 4 + i;
+  for (int i = 0; i < TR; ++i) {
+    const uint32_t r = ty * TR + i;
     if (m0 + r < M)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -1919,8 +1928,12 @@ void gemm_sq(const Ctx& c, const double* G, uint32_t s, const double* X, double*
   const uint32_t nks = s >= 512 ? cdiv(s, kSplitK) : 1;
   // one slice: the kernel's partial layout (rows of 64) is C itself
   double* P = nks > 1 ? c.d(c.SL->skpart) : C;
-  hipLaunchKernelGGL(k_gemm_splitk, dim3(cdiv(s, 64), nks), dim3(256), 0, c.st, G, s, X, kBlock, P, s,
-                     s, n, ch, c.stat(with_done));
+  if (n <= 32)
+    hipLaunchKernelGGL(k_gemm_splitk<32>, dim3(cdiv(s, 64), nks), dim3(256), 0, c.st, G, s, X, kBlock, P,
+                       s, s, n, ch, c.stat(with_done));
+  else
+    hipLaunchKernelGGL(k_gemm_splitk<64>, dim3(cdiv(s, 64), nks), dim3(256), 0, c.st, G, s, X, kBlock, P,
+                       s, s, n, ch, c.stat(with_done));
   if (nks > 1)
     hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv((uint64_t)s * 64, 256)), dim3(256), 0, c.st, P, nks,
                        s, C, kBlock, X, ch, c.stat(with_done));
