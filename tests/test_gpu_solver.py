@@ -297,3 +297,47 @@ def test_full_size_window(name, p, seed, sweeps):
     say(f"  core rel {rel(G, G_o):.2e}")
     assert rel(G, G_o) < CORE_REL
     np.testing.assert_allclose(G, G_o, rtol=0, atol=CORE_REL * np.abs(G_o).max())
+
+
+def test_block_iteration_hands_over_to_jacobi():
+    """A row-side Gram of side 48 at R = 12 whose eigenvalues 12..20 form a
+    cluster (relative spacing 2e-4) that straddles the block of 16: from a
+    random mode-0 factor the block iteration cannot pass its residual test
+    within its rounds, so the Jacobi solve launched behind it runs (cold),
+    and the sweep still matches the oracle's.  X (48 x 8 x 8, p = 1) has
+    X_(0) = U diag(s) V^T with orthonormal U, V and other ranks full, so the
+    mode-0 Gram of the sweep is X_(0) X_(0)^T whatever the other factors."""
+    import torch
+    from paper_0909_4969_amd import mach as M
+    rng = np.random.default_rng(23)
+    I, J, K = 48, 8, 8
+    s = np.concatenate([10.0 - 0.5 * np.arange(11), 1.0 - 1e-4 * np.arange(9)])
+    U = np.linalg.qr(rng.standard_normal((I, s.size)))[0]
+    V = np.linalg.qr(rng.standard_normal((J * K, s.size)))[0]
+    X = ((U * s) @ V.T).reshape(I, J, K).astype(np.float32)
+    ranks, p, seed = (12, 8, 8), 1.0, 24
+    dec = M.Decomposition(X.shape, ranks, p)
+    say("setup cluster", X.shape, ranks)
+    dec.sample(torch.from_numpy(X).cuda(), seed, 0)
+    Xh = O.sampled_tensor(X, p, seed, 0)
+    dec.hosvd()
+    A_in = O.hosvd_factors(Xh, ranks)
+    A_in[0] = np.linalg.qr(rng.standard_normal((I, ranks[0])))[0]
+    load_factors(dec, A_in)
+    say("sweep from a random mode-0 factor")
+    dec.sweep()
+    assert dec.status()[0] == 0
+    used = M.solver_stats(dec.solver)["jacobi_sweeps"][0]
+    say(f"  mode 0 statistics {used}")
+    assert 0 < used < 1000, used          # a cold Jacobi solve ran last
+    sing = {}
+    A_one, gaps, dk = oracle_sweep_with_gaps(Xh, A_in, ranks, sing=sing)
+    for n in range(3):
+        A_g = dec.factors[n].cpu().numpy()
+        np.testing.assert_allclose(A_g.T @ A_g, np.eye(ranks[n]), atol=1e-12)
+        st = sin_theta(A_one[n], A_g)
+        w = columns_elementwise(A_one[n], A_g, sing[n])
+        say(f"  mode {n}: sin_theta {st:.3e} gap {gaps[n]:.2e} tol {subspace_tol(gaps[n], dk[n]):.1e}; "
+            f"columns {w:.2e} of bound")
+        assert st <= subspace_tol(gaps[n], dk[n]), (n, st)
+        assert w <= 1.0, (n, w)
