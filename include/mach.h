@@ -194,7 +194,11 @@ mach_status mach_hosvd(const void* ws_sample, uint64_t nnz_cap, const mach_shape
  * indices, then float64) in every case.  Other prec values return
  * MACH_EUNSUPPORTED.  A short column-side mode (I_n <= 128,
  * 16 <= K_n <= 64, R_n <= 8) forms no Gram: its factor comes from a block
- * subspace iteration on Y Y^T in float64.
+ * subspace iteration on Y Y^T in float64.  The float64 eigensolve stops at
+ * an accuracy matched to its input: with MACH_F32 at off-diagonal mass
+ * 1e-16 of the diagonal (Jacobi) or Ritz residuals 1e-10 of the largest
+ * Ritz value (block and subspace iterations), with the other two at 1e-12
+ * and 1e-6, far below the rounding of their bfloat16 / e4m3 inputs.
  * A_dev (host array of d device pointers, I_n x R_n float64) is read and
  * the updated factors written back.  If fit_dev is not NULL, the device
  * double it points to receives 1 - ||Xhat - G x A|| / ||Xhat|| after the

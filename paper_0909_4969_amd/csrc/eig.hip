@@ -45,6 +45,20 @@ constexpr int kMaxSweeps = 40;
 // about 1e-7, so a tighter test would only resolve rounding noise.
 constexpr double kOffTol2 = 1e-16;
 
+// Stopping tolerances of a sweep's eigensolve, matched to the precision of
+// its input: with float32 TTM and Gram inputs, off-diagonal mass below 1e-16
+// of the diagonal mass (Jacobi) and Ritz residuals below 1e-10 of theta_1
+// (block and subspace iterations; above 1e-8 at the end is a failure); with
+// bfloat16 or e4m3 inputs, whose rounding perturbs the Gram by about 1e-3 of
+// its norm or more, 1e-12 and 1e-6 (1e-4): the eigensolve's own error stays
+// a thousand times below its input's.
+struct SolveTol {
+  double off2, res, res_fail;
+};
+__host__ __device__ inline SolveTol solve_tol(int prec) {
+  return prec == MACH_F32 ? SolveTol{kOffTol2, 1e-10, 1e-8} : SolveTol{1e-12, 1e-6, 1e-4};
+}
+
 // Round-robin pairing of NP indices (NP even): in round r < NP - 1, pair k
 // joins (r + k) mod (NP - 1) and (r - k) mod (NP - 1), and pair 0 joins r
 // and NP - 1; every pair of indices meets exactly once per sweep.
@@ -562,6 +576,7 @@ struct SsArgs {
   int32_t* done;           // OP 1: set to 1 when the residual test passed, else 0
   uint32_t O, I, Q, K, R;
   const double* Aprev;     // I x R, the current factor, or null
+  double rtol, rfail;      // residual test (relative to theta_1): pass, and failure at the end
   double* state;           // I x 16: the block of the last solve
   double* lam;             // >= 16
   int32_t* tag;
@@ -834,7 +849,8 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
     const double tau0 = a.lam[B - 1], ref0 = a.lam[0];
     if (tau0 > 1e-12 * ref0 && isfinite(tau0)) {
       filter(tau0, ref0);
-      filter(tau0, ref0);
+      // one application is enough for the looser test of mixed-precision inputs
+      if (a.rtol < 1e-7) filter(tau0, ref0);
     }
   }
   bool conv = false;
@@ -891,7 +907,7 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
       Qc = Zb;
       Zb = t;
     }
-    conv = worst <= 1e-10 * ref;
+    conv = worst <= a.rtol * ref;
     if (conv || it == MAXIT - 1) break;
     // tau = theta_16; two applications between Rayleigh-Ritz steps (one
     // seldom sufficed, and the step between would not change the span)
@@ -901,7 +917,7 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   // OP 1: a block that did not pass the test is dropped (the Jacobi solve
   // of the caller runs instead and leaves its own warm-start tag)
   if (OP == 1) {
-    const bool ok = conv || worst <= 1e-8 * ref;
+    const bool ok = conv || worst <= a.rfail * ref;
     if (tid == 0) *a.done = ok ? 1 : 0;
     if (!ok) return;
   }
@@ -929,7 +945,7 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   if (tid == 0) {
     *a.tag = a.tagval;
     if (a.stats) *a.stats = 3000 + it + 1;
-    if (OP != 1 && !conv && worst > 1e-8 * ref) atomicCAS(a.st.st, 0, MACH_ENOCONV);
+    if (OP != 1 && !conv && worst > a.rfail * ref) atomicCAS(a.st.st, 0, MACH_ENOCONV);
     if (OP == 0 && !(th[R - 1] > 1e-13 * th[0])) atomicCAS(a.st.st, 0, MACH_EDEGENERATE);
   }
 }
@@ -956,6 +972,7 @@ struct SolveArgs {
   double* Aout;
   float* af;
   int32_t* stats;
+  double tol2;            // Jacobi stopping threshold (off-diagonal / diagonal mass)
   Status st;
 };
 
@@ -1038,7 +1055,7 @@ __global__ __launch_bounds__(NT) void k_mode_solve(SolveArgs a) {
     jacobi_setup<NP, NT>(L, n, warm, a.V);
   }
   bool conv;
-  int used = jacobi_core<NP, NT>(L, n, (int)a.R, &conv);
+  int used = jacobi_core<NP, NT>(L, n, (int)a.R, &conv, a.tol2);
   jacobi_sort_store<NP, NT>(L, n, a.lam, a.V);
   if (tid == 0 && a.stats) *a.stats = used + (warm && a.ctc ? 2000 : warm ? 1000 : 0);
   if (tid < n && L.rk[tid] < (int)a.R) col_of_rank[L.rk[tid]] = tid;
@@ -1588,7 +1605,7 @@ __global__ void k_copy64(const double* __restrict__ src, double* __restrict__ ds
 // ||Z2[:,r] - theta_r Qr[:,r]|| <= tol * theta_0; single workgroup.
 __global__ __launch_bounds__(256) void k_ss_check(const double* __restrict__ Z2, const double* __restrict__ Qr,
                                                   uint32_t ld, uint32_t M, const double* __restrict__ theta,
-                                                  uint32_t R, double tol, int32_t* done, int last,
+                                                  uint32_t R, double tol, double tol_fail, int32_t* done, int last,
                                                   int32_t* stat_it, int32_t it, int32_t* ritz,
                                                   Status s) {
   if (s.skip()) return;
@@ -1621,7 +1638,7 @@ __global__ __launch_bounds__(256) void k_ss_check(const double* __restrict__ Z2,
       *stat_it = it + 1;
     } else if (last) {
       *stat_it = 10000 + it + 1;
-      if (worst > 1e-8 * ref) atomicCAS(s.st, 0, MACH_ENOCONV);
+      if (worst > tol_fail * ref) atomicCAS(s.st, 0, MACH_ENOCONV);
     }
   }
 }
@@ -2014,7 +2031,8 @@ double* orthonormalise(const Ctx& c, double* X, double* Y, uint32_t M, uint32_t 
 // start block (warm start if *tag == tagval); on return its first R columns
 // are the Ritz vectors and lam the Ritz values, descending.
 void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double* Q, double* lam,
-                   int32_t* tag, int32_t tagval, int maxit, int32_t* stat_it) {
+                   int32_t* tag, int32_t tagval, int maxit, int32_t* stat_it,
+                   SolveTol tol = solve_tol(MACH_F32)) {
   uint32_t b = 2 * R;
   b = b < 32 ? 32 : (b + 15) / 16 * 16;
   if (b > kBlock) b = kBlock;
@@ -2078,7 +2096,7 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
     double* zr = other(z, w);
     gemm(c, z, kBlock, VH, b, Qr, kBlock, s, b, b, true);
     gemm(c, w, kBlock, VH, b, zr, kBlock, s, b, b, true);
-    hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, zr, Qr, kBlock, s, lamH, R, 1e-10,
+    hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, zr, Qr, kBlock, s, lamH, R, tol.res, tol.res_fail,
                        tags + kTagDone, last ? 1 : 0, stat_it, it, tags + kTagRitz, c.stat(true));
     cur = Qr;
   }
@@ -2165,6 +2183,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
                               double* A_out, int prec, const SampleHdr* hdr, hipStream_t st) {
   Ctx c{&SL, ws, hdr, st};
   const ModePlan& m = SL.mp[k];
+  const SolveTol tol = solve_tol(prec);
   int32_t tagval = 0x4d000000 | (k << 16) | (int32_t)m.s;
   if (m.kside && m.I <= (uint32_t)kSsMaxI && m.K >= (uint32_t)kSsB && m.K <= (uint32_t)kSsMaxK &&
       m.R <= 8) {
@@ -2183,6 +2202,8 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     a.Aout = A_out;
     a.af = (float*)(ws + SL.af[k]);
     a.stats = (int32_t*)(ws + SL.status + 96) + k;
+    a.rtol = tol.res;
+    a.rfail = tol.res_fail;
     a.st = c.stat();
     hipLaunchKernelGGL((k_mode_ss<256, 0>), dim3(1), dim3(256), 0, st, a);
     return hipGetLastError();
@@ -2255,6 +2276,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     a.Aout = A_out;
     a.af = (float*)(ws + SL.af[k]);
     a.stats = (int32_t*)(ws + SL.status + 96) + k;
+    a.tol2 = tol.off2;
     a.st = c.stat();
     // Row-side Gram of side 33..64 and R <= 12: block iteration on the Gram
     // first (its own warm-start tag); the Jacobi solve runs, cold, only
@@ -2274,6 +2296,8 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
       g.Aout = A_out;
       g.af = (float*)(ws + SL.af[k]);
       g.stats = a.stats;
+      g.rtol = tol.res;
+      g.rfail = tol.res_fail;
       g.st = c.stat();
       hipLaunchKernelGGL((k_mode_ss<256, 1>), dim3(1), dim3(256), 0, st, g);
       a.st = c.stat(true);
@@ -2327,6 +2351,8 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     g.Aout = A_out;
     g.af = (float*)(ws + SL.af[k]);
     g.stats = (int32_t*)(ws + SL.status + 96) + k;
+    g.rtol = tol.res;
+    g.rfail = tol.res_fail;
     g.st = c.stat();
     hipLaunchKernelGGL((k_mode_ss<256, 2>), dim3(1), dim3(256), 0, st, g);
     return hipGetLastError();
@@ -2335,7 +2361,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
   double* V = c.d(m.Q64);
   const uint32_t ldv = kBlock;
   subspace_topk(c, G, m.s, m.R, V, c.d(m.lam), c.tags() + k, tagval, 24,
-                (int32_t*)(ws + SL.status + 96) + k);
+                (int32_t*)(ws + SL.status + 96) + k, tol);
   if (m.kside) {
     uint32_t J = m.O * m.Q;
     hipLaunchKernelGGL(k_backproject_dense, dim3(cdiv(m.I, 256)), dim3(256), 0, st,
@@ -2380,6 +2406,8 @@ hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const So
     g.Aout = A_out;
     g.af = (float*)(ws + SL.af[n]);
     g.stats = (int32_t*)(ws + SL.status + 128) + n;
+    g.rtol = solve_tol(MACH_F32).res;
+    g.rfail = solve_tol(MACH_F32).res_fail;
     g.st = c.stat();
     hipLaunchKernelGGL((k_mode_ss<256, 2>), dim3(1), dim3(256), 0, st, g);
     return hipGetLastError();
