@@ -1205,31 +1205,33 @@ __global__ __launch_bounds__(256) void k_chol_apply_tall(double* __restrict__ Aw
     for (int r = 0; r < 16; ++r) Aw[(size_t)i * 16 + r] = out[r];
   }
   // column maxima over this workgroup's rows (value, then lowest row):
-  // butterfly within each wave, then the 4 wave results in order.
-  const int lane = tid & 63, wv = tid >> 6;
-  for (int r = 0; r < 16; ++r) {
-    double v = i < I ? fabs(out[r]) : -1.0;
-    uint32_t ix = i;
-    for (int m = 1; m < 64; m <<= 1) {
-      double v2 = __shfl_xor(v, m, 64);
-      uint32_t i2 = __shfl_xor(ix, m, 64);
-      if (v2 > v || (v2 == v && i2 < ix)) {
-        v = v2;
-        ix = i2;
+  // |q| through LDS, thread (g, c) scans rows g, g + 16, ... of column c in
+  // increasing order, then 16 threads take the 16 group results in order.
+  __shared__ double aq[256][17];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) aq[tid][r] = i < I ? fabs(out[r]) : -1.0;
+  __syncthreads();
+  {
+    const int cidx = tid & 15, g = tid >> 4;
+    double v = -1.0;
+    uint32_t ix = 0xffffffffu;
+    for (int row = g; row < 256; row += 16) {
+      const double x = aq[row][cidx];
+      if (x > v) {
+        v = x;
+        ix = blockIdx.x * 256 + row;
       }
     }
-    if (lane == 0) {
-      bv[wv * 16 + r] = v;
-      bi[wv * 16 + r] = ix;
-    }
+    bv[tid] = v;
+    bi[tid] = ix;
   }
   __syncthreads();
   if (tid < 16) {
-    double v = bv[tid];
-    uint32_t ix = bi[tid];
-    for (int w2 = 1; w2 < 4; ++w2) {
-      double v2 = bv[w2 * 16 + tid];
-      uint32_t i2 = bi[w2 * 16 + tid];
+    double v = -1.0;
+    uint32_t ix = 0xffffffffu;
+    for (int g = 0; g < 16; ++g) {
+      const double v2 = bv[g * 16 + tid];
+      const uint32_t i2 = bi[g * 16 + tid];
       if (v2 > v || (v2 == v && i2 < ix)) {
         v = v2;
         ix = i2;
