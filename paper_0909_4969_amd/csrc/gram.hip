@@ -196,7 +196,24 @@ hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream
 // holds the even columns' sum when r comes first, the odd columns' sum when
 // r comes last, and k_gram_mirror adds the two halves of every pair.
 // Row r = v / 2 for even wave index v and MH - 1 - v / 2 for odd v.
+//
+// The walk is bound by its reads of the column lists, so the row's entries
+// go in groups of kSgU and the first kSgC 64-entry chunks of every part in
+// a group are loaded, unconditionally, before any is added (a part of a
+// column of up to 256 entries needs no further load; longer ones finish in
+// a loop).  The additions are LDS float64 atomic adds whose result is not
+// read back: the wave owns its accumulator row and LDS operations of one
+// wave complete in the order they are issued, so every accumulator still
+// takes its terms in column order, each product v v' of two float32 values
+// is exact in float64, and every sum is rounded exactly as a plain
+// read-add-write would round it.
 constexpr uint32_t kSparseGramMaxRows = 2048;
+constexpr int kSgU = 4, kSgC = 4;
+
+__device__ __forceinline__ void sg_add(double* row, FastDiv fMT, Entry b, double vk) {
+  __hip_atomic_fetch_add(&row[fMT.div(b.l)], vk * (double)b.v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 __global__ __launch_bounds__(256) void k_gram_rows_sparse(uint32_t MH, FastDiv fMT,
                                                           const uint32_t* __restrict__ headpos,
@@ -237,27 +254,30 @@ __global__ __launch_bounds__(256) void k_gram_rows_sparse(uint32_t MH, FastDiv f
         }
       }
       const int cnt = (int)min(64u, e1 - e0);
-      for (int k = 0; k < cnt; k += 4) {
-        // first column chunk of four entries loaded before any is added
-        Entry b[4];
-        uint32_t f[4], h[4];
-        double vk[4];
+      for (int k = 0; k < cnt; k += kSgU) {
+        Entry b[kSgC][kSgU];
+        uint32_t f[kSgU], h[kSgU];
+        double vk[kSgU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kSgU; ++u) {
           const int ku = min(k + u, cnt - 1);
           f[u] = (uint32_t)__builtin_amdgcn_readlane((int)lo, ku) + lane;
           h[u] = k + u < cnt ? (uint32_t)__builtin_amdgcn_readlane((int)hi, ku) : 0u;
           vk[u] = (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, va), ku));
-          b[u] = f[u] < h[u] ? coo_t[f[u]] : Entry{0u, 0.0f};
+          // Unconditional loads (a predicated load is compiled to a branch
+          // that waits for it): lanes past the part read its last entry, or
+          // entry 0 where the group has no entry u (the row's own entries
+          // make the list non-empty); their terms are not added.
+          const uint32_t last = h[u] > 0u ? h[u] - 1u : 0u;
+#pragma unroll
+          for (int j = 0; j < kSgC; ++j) b[j][u] = coo_t[min(f[u] + 64u * j, last)];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (f[u] < h[u]) row[fMT.div(b[u].l)] += vk[u] * (double)b[u].v;
-          for (uint32_t g = f[u] + 64; g < h[u]; g += 64) {
-            const Entry bb = coo_t[g];
-            row[fMT.div(bb.l)] += vk[u] * (double)bb.v;
-          }
-          __builtin_amdgcn_wave_barrier();
+        for (int u = 0; u < kSgU; ++u) {
+#pragma unroll
+          for (int j = 0; j < kSgC; ++j)
+            if (f[u] + 64u * j < h[u]) sg_add(row, fMT, b[j][u], vk[u]);
+          for (uint32_t g = f[u] + 64u * kSgC; g < h[u]; g += 64) sg_add(row, fMT, coo_t[g], vk[u]);
         }
       }
     }
