@@ -1347,21 +1347,16 @@ struct Cheb {
   const double* Xp;       // input of step 1 (step 2 only), ld kBlock
 };
 
-__device__ __forceinline__ void cheb_coef(const Cheb& ch, double* al, double* be, double* ga) {
-  *al = 1.0;
-  *be = 0.0;
-  *ga = 0.0;
-  if (ch.step == 0 || !ch.valid || *ch.valid == 0) return;
+struct ChebCoef {
+  double al, be, ga;
+};
+
+__device__ __forceinline__ ChebCoef cheb_coef(const Cheb& ch) {
+  if (ch.step == 0 || !ch.valid || *ch.valid == 0) return ChebCoef{1.0, 0.0, 0.0};
   const double tau = ch.lam[ch.bidx];
-  if (!(tau > 0.0) || !isfinite(tau)) return;
-  if (ch.step == 1) {
-    *al = 2.0 / tau;
-    *be = -1.0;
-  } else {
-    *al = 4.0 / tau;
-    *be = -2.0;
-    *ga = -1.0;
-  }
+  if (!(tau > 0.0) || !isfinite(tau)) return ChebCoef{1.0, 0.0, 0.0};
+  if (ch.step == 1) return ChebCoef{2.0 / tau, -1.0, 0.0};
+  return ChebCoef{4.0 / tau, -2.0, -1.0};
 }
 
 // C[M x N] partials of A[M x K] * B[K x N] (row-major, N <= NC) for long K:
@@ -1371,6 +1366,45 @@ __device__ __forceinline__ void cheb_coef(const Cheb& ch, double* al, double* be
 // staged in LDS (A transposed); each thread accumulates a block of
 // 64 / (256 / (NC / 4)) rows x 4 columns in float64 (4 x 4 for NC = 64,
 // 2 x 4 for NC = 32).
+// One 32-index tile of the split product: A rows m0..m0+63, B columns
+// 0..NC-1.  Loads are unconditional, at indices clamped into A and B (a
+// predicated load, or a select that the compiler turns back into one, is
+// compiled to a branch that waits for the load); splitk_stage zeroes the
+// entries outside the tile by a factor 0 when it stores them to LDS, so
+// that nothing waits for the loads before then.
+template <int NC>
+__device__ __forceinline__ void splitk_fetch(const double* __restrict__ A, uint32_t lda,
+                                             const double* __restrict__ B, uint32_t ldb, uint32_t M,
+                                             uint32_t N, uint32_t m0, uint32_t kc, uint32_t k1, int tid,
+                                             double (&va)[8], double (&vb)[NC / 8]) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int e = tid + 256 * t, r = e >> 5, kk = e & 31;
+    va[t] = A[(size_t)min(m0 + r, M - 1) * lda + min(kc + kk, k1 - 1)];
+  }
+#pragma unroll
+  for (int t = 0; t < NC / 8; ++t) {
+    const int e = tid + 256 * t, kb = e / NC, cb = e % NC;
+    vb[t] = B[(size_t)min(kc + kb, k1 - 1) * ldb + min((uint32_t)cb, N - 1)];
+  }
+}
+
+template <int NC>
+__device__ __forceinline__ void splitk_stage(double (*As)[68], double (*Bs)[68], uint32_t M, uint32_t N,
+                                             uint32_t m0, uint32_t kc, uint32_t k1, int tid,
+                                             const double (&va)[8], const double (&vb)[NC / 8]) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int e = tid + 256 * t, r = e >> 5, kk = e & 31;
+    As[kk][r] = va[t] * ((m0 + r < M && kc + kk < k1) ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int t = 0; t < NC / 8; ++t) {
+    const int e = tid + 256 * t, kb = e / NC, cb = e % NC;
+    Bs[kb][cb] = vb[t] * ((kc + kb < k1 && (uint32_t)cb < N) ? 1.0 : 0.0);
+  }
+}
+
 template <int NC>
 __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ A, uint32_t lda,
                                                      const double* __restrict__ B, uint32_t ldb,
@@ -1389,24 +1423,13 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ 
   for (int i = 0; i < TR; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  // the next tile's loads are in flight while the current one is multiplied
+  double va[8], vb[NC / 8];
+  if (k0 < k1) splitk_fetch<NC>(A, lda, B, ldb, M, N, m0, k0, k1, tid, va, vb);
   for (uint32_t kc = k0; kc < k1; kc += 32) {
-    double va[8], vb[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + 256 * t, r = e >> 5, kk = e & 31;
-      const uint32_t m = m0 + r, k = kc + kk;
-      va[t] = (m < M && k < k1) ? A[(size_t)m * lda + k] : 0.0;
-      const int kb = e >> 6, cb = e & 63;
-      const uint32_t k2 = kc + kb;
-      vb[t] = (k2 < k1 && (uint32_t)cb < N) ? B[(size_t)k2 * ldb + cb] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + 256 * t;
-      As[e & 31][e >> 5] = va[t];
-      Bs[e >> 6][e & 63] = vb[t];
-    }
+    splitk_stage<NC>(As, Bs, M, N, m0, kc, k1, tid, va, vb);
     __syncthreads();
+    if (kc + 32 < k1) splitk_fetch<NC>(A, lda, B, ldb, M, N, m0, kc + 32, k1, tid, va, vb);
 #pragma unroll 8
     for (int kk = 0; kk < 32; ++kk) {
       double a[TR], b[4];
@@ -1422,8 +1445,9 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(const double* __restrict__ 
     __syncthreads();
   }
   double* o = P + ((size_t)blockIdx.y * M + m0) * 64;
-  double al = 1.0, be = 0.0, ga = 0.0;
-  if (gridDim.y == 1) cheb_coef(ch, &al, &be, &ga);   // single slice: P is the output
+  // single slice: P is the output, with the filter epilogue
+  const ChebCoef cf = gridDim.y == 1 ? cheb_coef(ch) : ChebCoef{1.0, 0.0, 0.0};
+  const double al = cf.al, be = cf.be, ga = cf.ga;
   if (NC < 64)   // the columns this variant does not compute
     for (int e = tid; e < 64 * (64 - NC); e += 256) {
       const uint32_t r = e / (64 - NC), cidx = NC + e % (64 - NC);
@@ -1452,10 +1476,18 @@ __global__ void k_splitk_reduce(const double* __restrict__ P, uint32_t nks, uint
   if (s.skip()) return;
   const uint32_t e = blockIdx.x * 256 + threadIdx.x;
   if (e >= M * 64) return;
+  // the slices in order, eight loads in flight (unconditional, clamped to
+  // the last slice; a slice past the end adds +-0, which changes no sum)
   double acc = 0.0;
-  for (uint32_t k = 0; k < nks; ++k) acc += P[(size_t)k * M * 64 + e];
-  double al, be, ga;
-  cheb_coef(ch, &al, &be, &ga);
+  for (uint32_t k0 = 0; k0 < nks; k0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = P[(size_t)min(k0 + u, nks - 1) * M * 64 + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u] * (k0 + u < nks ? 1.0 : 0.0);
+  }
+  const ChebCoef cf = cheb_coef(ch);
+  const double al = cf.al, be = cf.be, ga = cf.ga;
   const size_t o = (size_t)(e >> 6) * ldc + (e & 63);
   double v = al * acc;
   if (be != 0.0) v = fma(be, X[o], v);
@@ -1734,13 +1766,14 @@ __global__ __launch_bounds__(256) void k_backproject_cols(const Entry* __restric
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0;
   if (i < I) {
+    // all 16 factor entries of a row are loaded unconditionally (columns
+    // from R on repeat column R - 1, inside the row; their sums are unused)
     for (uint32_t e = colptr[i] + lane; e < colptr[i + 1]; e += 64) {
       Entry en = coo_t[e];
       const double* v = V + (size_t)fMT.div(en.l) * ldv;
       double x = (double)en.v;
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        if ((uint32_t)r < R) acc[r] = fma(x, v[r], acc[r]);
+      for (int r = 0; r < 16; ++r) acc[r] = fma(x, v[min((uint32_t)r, R - 1)], acc[r]);
     }
   }
 #pragma unroll
@@ -2114,7 +2147,10 @@ __global__ __launch_bounds__(256) void k_ata16_partial(const double* __restrict_
   __shared__ double rows[256][17];
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) rows[threadIdx.x][r] = i < I ? Aw[(size_t)i * 16 + r] : 0.0;
+  for (int r = 0; r < 16; ++r) {
+    const double x = Aw[(size_t)min(i, I - 1) * 16 + r];   // unconditional load
+    rows[threadIdx.x][r] = i < I ? x : 0.0;
+  }
   __syncthreads();
   const int x = threadIdx.x >> 4, y = threadIdx.x & 15;
   double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
