@@ -44,7 +44,7 @@ constexpr uint32_t kBlock = 64;          // subspace block for sides > kSmallEig
 // sred: Gram of a sweep mode (64 x 64), C_j of up to 3 other modes (3 x 256),
 // 16 x 16 Gram of a tall factor
 constexpr uint32_t kSredGram = 0, kSredCtc = 4096, kSredTall = 4096 + 768, kSredElems = 4096 + 768 + 256;
-constexpr uint32_t kSplitK = 256;        // summation slice of the split products by G
+constexpr uint32_t kSplitK = 128;        // summation slice of the split products by G
 constexpr uint32_t kMfmaGramMaxRows = 1024;  // row-side HOSVD Grams on MFMA up to this side
 // Tiled head-row pass: the tail factor is tiled when its float32 copy (16
 // columns) exceeds kTiledFactorBytes; tiles span kTileTicksMin..kTileTicksMax
