@@ -571,6 +571,8 @@ __global__ void k_headrow(ShapeInfo si, uint32_t* __restrict__ headrow, uint32_t
 }
 
 // Wave = (64 consecutive tail columns) x (one block of rb head rows).
+constexpr int kCscRows = 8;   // rows of a CSC count / fill group
+
 __global__ __launch_bounds__(256) void k_csc_count(ShapeInfo si, const uint64_t* __restrict__ bitmap,
                                                    const uint32_t* __restrict__ headrow,
                                                    uint32_t* __restrict__ cnt) {
@@ -579,9 +581,19 @@ __global__ __launch_bounds__(256) void k_csc_count(ShapeInfo si, const uint64_t*
   if (rb >= si.nrb || c >= si.MT) return;
   uint32_t t0 = rb * si.rb, t1 = min(si.MH, t0 + si.rb);
   uint32_t n = 0;
-  for (uint32_t t = t0; t < t1; ++t) {
-    uint32_t l = headrow[t] * si.MT + c;
-    n += (uint32_t)(bitmap[l >> 6] >> (l & 63)) & 1u;
+  // rows in groups of kCscRows, their loads issued before any is used
+  // (indices clamped to the block's last row; the extra rows are not counted)
+  for (uint32_t tb = t0; tb < t1; tb += kCscRows) {
+    uint64_t word[kCscRows];
+    uint32_t l[kCscRows];
+#pragma unroll
+    for (int u = 0; u < kCscRows; ++u) {
+      l[u] = headrow[min(tb + u, t1 - 1)] * si.MT + c;
+      word[u] = bitmap[l[u] >> 6];
+    }
+#pragma unroll
+    for (int u = 0; u < kCscRows; ++u)
+      n += tb + u < t1 ? (uint32_t)(word[u] >> (l[u] & 63)) & 1u : 0u;
   }
   cnt[c * si.nrb + rb] = n;
 }
@@ -603,19 +615,38 @@ __global__ __launch_bounds__(256) void k_csc_fill(ShapeInfo si, const uint64_t* 
     uint64_t nnz = hdr->nnz;
     colptr[si.MT] = (uint32_t)(nnz < cap ? nnz : cap);
   }
+  if (cap == 0) return;
   uint32_t t0 = rb * si.rb, t1 = min(si.MH, t0 + si.rb);
-  for (uint32_t t = t0; t < t1; ++t) {
-    uint32_t l = headrow[t] * si.MT + c;
-    uint64_t word = bitmap[l >> 6];
-    uint32_t b = l & 63;
-    if ((word >> b) & 1ull) {
-      uint64_t below = b ? (word & ((~0ull) >> (64 - b))) : 0ull;
-      uint64_t src = (uint64_t)wrank[l >> 6] + (uint32_t)__popcll(below);
-      if (src < cap && dest < cap) {
-        coo_t[dest] = coo_l[src];
-        cscpos[src] = (uint32_t)dest;
+  // Rows in groups of kCscRows: the bitmap words and word ranks of the group,
+  // then its entries, are loaded before any is used (indices clamped to the
+  // block's last row and to the kept list; the extra loads are not used), and
+  // the kept entries are placed in row order as before.
+  for (uint32_t tb = t0; tb < t1; tb += kCscRows) {
+    uint64_t word[kCscRows], src[kCscRows];
+    uint32_t l[kCscRows], wr[kCscRows];
+    Entry en[kCscRows];
+#pragma unroll
+    for (int u = 0; u < kCscRows; ++u) {
+      l[u] = headrow[min(tb + u, t1 - 1)] * si.MT + c;
+      word[u] = bitmap[l[u] >> 6];
+      wr[u] = wrank[l[u] >> 6];
+    }
+#pragma unroll
+    for (int u = 0; u < kCscRows; ++u) {
+      const uint32_t b = l[u] & 63;
+      const uint64_t below = b ? (word[u] & ((~0ull) >> (64 - b))) : 0ull;
+      src[u] = (uint64_t)wr[u] + (uint32_t)__popcll(below);
+      en[u] = coo_l[src[u] < cap ? src[u] : cap - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kCscRows; ++u) {
+      if (tb + u < t1 && ((word[u] >> (l[u] & 63)) & 1ull)) {
+        if (src[u] < cap && dest < cap) {
+          coo_t[dest] = en[u];
+          cscpos[src[u]] = (uint32_t)dest;
+        }
+        ++dest;
       }
-      ++dest;
     }
   }
 }
