@@ -712,9 +712,20 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
   // eight loads per thread issued before their LDS stores
   static_assert(kSsMaxI * kSsMaxK % (8 * NT) == 0, "Y load in groups of eight");
   if (OP == 1) {   // G (I x I, I <= 64) in Y, zero padded
-    for (int e = tid; e < kSsMaxK * kSsMaxK; e += NT) {
-      const int i = e / kSsMaxK, k = e % kSsMaxK;
-      Y[i][k] = (i < I && k < I) ? a.G[(size_t)i * I + k] : 0.0;
+    // unconditional loads at clamped indices (entries of G, finite), the
+    // padding zeroed by a factor 0: a predicated load, or a select the
+    // compiler turns back into one, is a branch that waits for the load
+    constexpr int NL = kSsMaxK * kSsMaxK / NT;
+    double g[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = u * NT + tid, i = e / kSsMaxK, k = e % kSsMaxK;
+      g[u] = a.G[(size_t)min(i, I - 1) * I + min(k, I - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = u * NT + tid, i = e / kSsMaxK, k = e % kSsMaxK;
+      Y[i][k] = g[u] * ((i < I && k < I) ? 1.0 : 0.0);
     }
   }
   for (int e0 = 0; e0 < (GRAM ? 0 : kSsMaxI * kSsMaxK); e0 += 8 * NT) {
@@ -734,30 +745,50 @@ __global__ __launch_bounds__(NT) void k_mode_ss(SsArgs a) {
       Y[e / kSsMaxK][e % kSsMaxK] = (double)v[u];
     }
   }
+  // Start block: the previous solve's block (warm), else the current factor
+  // completed by fixed pseudo-random columns, else those columns only.  The
+  // source is the same for every thread; within it the eight loads of a
+  // thread are unconditional, at indices clamped into the source (finite
+  // values), and rows past I are zeroed by a factor 0.
   const bool warm = *a.tag == a.tagval;
+  const int src = warm ? 0 : (a.Aprev ? 1 : 2);
+  auto hashval = [](int i, int j) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(j + 1) * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return (double)(h >> 8) * (1.0 / 16777216.0) - 0.5;
+  };
   static_assert(MAXI * B % (8 * NT) == 0, "start block loaded eight values per thread at a time");
   for (int e0 = 0; e0 < MAXI * B; e0 += 8 * NT) {
     double v[8];
+    if (src == 0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * NT + tid, i = e / B, j = e % B;
-      v[u] = 0.0;
-      if (i < I) {
-        if (warm) v[u] = a.state[i * B + j];
-        else if (j < R && a.Aprev) v[u] = a.Aprev[(size_t)i * R + j];
-        else {
-          uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(j + 1) * 0x85EBCA77u;
-          h ^= h >> 15;
-          h *= 0x2C1B3C6Du;
-          h ^= h >> 12;
-          v[u] = (double)(h >> 8) * (1.0 / 16777216.0) - 0.5;
-        }
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * NT + tid, i = e / B, j = e % B;
+        v[u] = a.state[min(i, I - 1) * B + j];
+      }
+    } else if (src == 1) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * NT + tid, i = e / B, j = e % B;
+        v[u] = a.Aprev[(size_t)min(i, I - 1) * R + min(j, R - 1)];
       }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * NT + tid;
-      Q0[e / B][e % B] = v[u];
+      const int e = e0 + u * NT + tid, i = e / B, j = e % B;
+      const double row = i < I ? 1.0 : 0.0;
+      double x;
+      if (src == 0) {
+        x = v[u] * row;
+      } else if (src == 1) {
+        const double own = j < R ? 1.0 : 0.0;
+        x = (v[u] * own + hashval(i, j) * (1.0 - own)) * row;
+      } else {
+        x = hashval(i, j) * row;
+      }
+      Q0[e / B][e % B] = x;
     }
   }
   __syncthreads();
