@@ -221,14 +221,71 @@ __device__ void lds_gemm(double (*A)[NP + 1], double (*B)[NP + 1], double (*D)[N
 // row-major, when warm), or the one already in L.V (in_lds) — and, unless it
 // is the identity, replaces L.A = G by V^T G V.  Expects L.A = G (padded
 // with zeros).
+// V (NP x NP in LDS) = Vin (n x n row-major) padded with the identity, or
+// the identity when !use.  The loads are unconditional, at indices clamped
+// into Vin (finite entries), and the padding is set by factors 0 and 1: a
+// predicated load, or a select the compiler turns back into one, is a branch
+// that waits for its load.
+template <int NP, int NT>
+__device__ __forceinline__ void load_basis(double (*V)[NP + 1], int n, bool use, const double* Vin) {
+  static_assert(NP * NP % NT == 0, "whole entries per thread");
+  constexpr int NE = NP * NP / NT;
+  const int tid = threadIdx.x;
+  double v[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) v[u] = 0.0;
+  if (use) {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = u * NT + tid, x = e / NP, y = e % NP;
+      v[u] = Vin[min(x, n - 1) * n + min(y, n - 1)];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = u * NT + tid, x = e / NP, y = e % NP;
+    const double m = (use && x < n && y < n) ? 1.0 : 0.0;
+    V[x][y] = v[u] * m + (1.0 - m) * (x == y ? 1.0 : 0.0);
+  }
+}
+
+// A (NP x NP in LDS) = the n x n matrix summed from its chunk partials
+// (part[(x n + y) nchunk + c]), zero padded, each entry summed in chunk
+// order; loads unconditional at clamped indices, the padding zeroed by a
+// factor 0 (as in load_basis).
+template <int NP, int NT>
+__device__ __forceinline__ void load_gram(double (*A)[NP + 1], int n, const double* part,
+                                          uint32_t nchunk) {
+  static_assert(NP * NP % NT == 0, "whole entries per thread");
+  constexpr int NE = NP * NP / NT;
+  const int tid = threadIdx.x;
+  double g[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) g[u] = 0.0;
+  for (uint32_t c = 0; c < nchunk; ++c) {
+    double p[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = u * NT + tid, x = e / NP, y = e % NP;
+      p[u] = part[(size_t)(min(x, n - 1) * n + min(y, n - 1)) * nchunk + c];
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = u * NT + tid, x = e / NP, y = e % NP;
+      g[u] += p[u] * ((x < n && y < n) ? 1.0 : 0.0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = u * NT + tid;
+    A[e / NP][e % NP] = g[u];
+  }
+}
+
 template <int NP, int NT>
 __device__ void jacobi_setup(JacLds<NP>& L, int n, bool warm, const double* Vin, bool in_lds = false) {
   const int tid = threadIdx.x;
-  if (!in_lds)
-    for (int e = tid; e < NP * NP; e += NT) {
-      int x = e / NP, y = e % NP;
-      L.V[x][y] = (warm && x < n && y < n) ? Vin[x * n + y] : (x == y ? 1.0 : 0.0);
-    }
+  if (!in_lds) load_basis<NP, NT>(L.V, n, warm, Vin);
   warm = warm || in_lds;
   __syncthreads();
   if (!warm) return;
@@ -423,16 +480,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_small(JacArgs a) {
   __shared__ JacLds<NP> L;
   const int n = (int)a.n, tid = threadIdx.x;
   const bool warm = a.tagval != 0 && *a.tag == a.tagval;
-  for (int e = tid; e < NP * NP; e += NT) {
-    int x = e / NP, y = e % NP;
-    double g = 0.0;
-    if (x < n && y < n) {
-      const double* p = a.G + (size_t)(x * n + y) * a.nchunk;
-#pragma unroll 16
-      for (uint32_t c = 0; c < a.nchunk; ++c) g += p[c];
-    }
-    L.A[x][y] = g;
-  }
+  load_gram<NP, NT>(L.A, n, a.G, a.nchunk);
   __syncthreads();
   jacobi_setup<NP, NT>(L, n, warm, a.V);
   bool conv;
@@ -1014,16 +1062,7 @@ __global__ __launch_bounds__(NT) void k_mode_solve(SolveArgs a) {
   __shared__ double sgn[16];
   __shared__ int col_of_rank[16];
   const int n = (int)a.s, tid = threadIdx.x;
-  for (int e = tid; e < NP * NP; e += NT) {
-    int x = e / NP, y = e % NP;
-    double g = 0.0;
-    if (x < n && y < n) {
-      const double* p = a.part + (size_t)(x * n + y) * a.nchunk;
-#pragma unroll 8
-      for (uint32_t c = 0; c < a.nchunk; ++c) g += p[c];
-    }
-    L.A[x][y] = g;
-  }
+  load_gram<NP, NT>(L.A, n, a.part, a.nchunk);
   __syncthreads();
   bool warm = (*a.tag == a.tagval);
   if (warm && a.ctc) {
@@ -1036,10 +1075,7 @@ __global__ __launch_bounds__(NT) void k_mode_solve(SolveArgs a) {
       for (uint32_t c = 0; c < nc; ++c) v += p[c];
       Cj[e >> 8][(e >> 4) & 15][e & 15] = v;
     }
-    for (int e = tid; e < NP * NP; e += NT) {
-      const int x = e / NP, y = e % NP;
-      L.V[x][y] = (x < n && y < n) ? a.V[x * n + y] : (x == y ? 1.0 : 0.0);
-    }
+    load_basis<NP, NT>(L.V, n, true, a.V);
     __syncthreads();
     // P[x][y] = prod_j C_j[(x / st_j) % R_j][(y / st_j) % R_j]
     for (int e = tid; e < NP * NP; e += NT) {
