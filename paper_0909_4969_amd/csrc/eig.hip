@@ -1902,17 +1902,25 @@ __global__ __launch_bounds__(256) void k_sign_store(const double* __restrict__ A
   {
     // column r = tid % 16: 16 threads scan the chunk maxima, then one
     // combines them (largest value, lowest row on ties: order-free)
+    // (four chunks per round, loaded unconditionally at clamped indices)
     const uint32_t r = threadIdx.x & 15, g = threadIdx.x >> 4;
     double b = -1.0;
     uint32_t bx = 0xffffffffu;
-#pragma unroll 4
-    for (uint32_t c = g; c < nchunk; c += 16) {
-      const double v = pv[c * 16 + r];
-      const uint32_t ix = pi[c * 16 + r];
-      if (v > b || (v == b && ix < bx)) {
-        b = v;
-        bx = ix;
+    for (uint32_t c0 = g; c0 < nchunk; c0 += 64) {
+      double v[4];
+      uint32_t ix[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t c = min(c0 + 16u * u, nchunk - 1);
+        v[u] = pv[c * 16 + r];
+        ix[u] = pi[c * 16 + r];
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (c0 + 16u * u < nchunk && (v[u] > b || (v[u] == b && ix[u] < bx))) {
+          b = v[u];
+          bx = ix[u];
+        }
     }
     bv[threadIdx.x] = b;
     bi[threadIdx.x] = bx;

@@ -377,6 +377,24 @@ __global__ __launch_bounds__(kThreads) void k_sample_compact(const XT* __restric
   __syncthreads();
   double ss = 0.0;
   const uint32_t base_elem = b * kSampleBlockElems;
+  // The X loads of all 16 groups of four elements (those with a kept entry)
+  // are issued before any entry is written.
+  XT xs[16][4];
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const uint32_t g = it * kThreads + threadIdx.x;
+    const uint32_t e0 = base_elem + 4u * g;
+    const uint32_t nib = (uint32_t)(words[g >> 4] >> ((g & 15u) * 4u)) & 15u;
+    if (nib != 0) {
+      if (e0 + 3 < N) {
+        load4(X + e0, xs[it]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xs[it][k] = (e0 + k < N) ? X[e0 + k] : (XT)0;
+      }
+    }
+  }
+#pragma unroll
   for (int it = 0; it < 16; ++it) {
     uint32_t g = it * kThreads + threadIdx.x;
     uint32_t e0 = base_elem + 4u * g;
@@ -386,13 +404,7 @@ __global__ __launch_bounds__(kThreads) void k_sample_compact(const XT* __restric
     if (nib == 0) continue;
     uint64_t below = sh4 ? (word & ((~0ull) >> (64 - sh4))) : 0ull;
     uint64_t r = (uint64_t)off + lrank[wi] + (uint32_t)__popcll(below);
-    XT x[4];
-    if (e0 + 3 < N) {
-      load4(X + e0, x);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) x[k] = (e0 + k < N) ? X[e0 + k] : (XT)0;
-    }
+    const XT* x = xs[it];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if ((nib >> k) & 1u) {
