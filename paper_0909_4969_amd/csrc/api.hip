@@ -282,7 +282,12 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
     if (m.R > S.hosvd_s[k]) return false;
     if (S.hosvd_s[k] > (uint32_t)kSmallEig && S.hosvd_s[k] > zrows) zrows = S.hosvd_s[k];
     if (!S.hosvd_kside[k] && S.hosvd_s[k] > hs_iside_max) hs_iside_max = S.hosvd_s[k];
-    gmax = std::max(gmax, (size_t)S.hosvd_s[k] * S.hosvd_s[k]);
+    // the single tail mode's column-side Gram with more head rows than the
+    // sparse Gram holds is never formed
+    if (k == d - 1 && h == d - 1 && S.hosvd_kside[k] && si.MH > kSparseGramMaxRows)
+      S.hosvd_gram_free = 1;
+    else
+      gmax = std::max(gmax, (size_t)S.hosvd_s[k] * S.hosvd_s[k]);
   }
   // Views of Y_k (see solver.h).
   const uint32_t* I = si.dims;
@@ -393,13 +398,15 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
   S.pi = take(1024 * 16 * 4);
   S.tags = S.status + 16;
   S.sred = take((size_t)kSredElems * 8);
+  const size_t gfw_bytes = S.hosvd_gram_free ? (size_t)si.MT * 32 * 8 : 0;
+  S.gfw = take(gfw_bytes);
   if (d >= 2) {   // second scratch copy for the last mode's HOSVD
-    const size_t sz[17] = {gmax * 8, S.Gpart_elems * 8, (size_t)imax * 16 * 8,
+    const size_t sz[18] = {gmax * 8, S.Gpart_elems * 8, (size_t)imax * 16 * 8,
                            (size_t)zrows * kBlock * 8, (size_t)zrows * kBlock * 8,
                            (size_t)zrows * kBlock * 8, (size_t)zrows * kBlock * 8, 64 * 64 * 8,
                            64 * 64 * 8, 64 * 64 * 8, 64 * 8, 64 * 64 * 64 * 8, skmax * 8,
-                           1024 * 16 * 8, 1024 * 16 * 4, 256, (size_t)kSredElems * 8};
-    for (int f = 0; f < 17; ++f) S.laneb[f] = take(sz[f]);
+                           1024 * 16 * 8, 1024 * 16 * 4, 256, (size_t)kSredElems * 8, gfw_bytes};
+    for (int f = 0; f < 18; ++f) S.laneb[f] = take(sz[f]);
   }
   S.total = o;
   *out = S;
@@ -408,9 +415,9 @@ bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout*
 
 SolverLayout solver_lane_b(const SolverLayout& S) {
   SolverLayout B = S;
-  size_t* f[17] = {&B.G, &B.Gpart, &B.Aw, &B.Zs, &B.Z2s, &B.Qrs, &B.Qhs, &B.H,   &B.VH,
-                   &B.small, &B.lamH, &B.part, &B.skpart, &B.pv, &B.pi, &B.tags, &B.sred};
-  for (int i = 0; i < 17; ++i) *f[i] = S.laneb[i];
+  size_t* f[18] = {&B.G,     &B.Gpart, &B.Aw, &B.Zs,     &B.Z2s, &B.Qrs, &B.Qhs,  &B.H,    &B.VH,
+                   &B.small, &B.lamH,  &B.part, &B.skpart, &B.pv,  &B.pi,  &B.tags, &B.sred, &B.gfw};
+  for (int i = 0; i < 18; ++i) *f[i] = S.laneb[i];
   return B;
 }
 

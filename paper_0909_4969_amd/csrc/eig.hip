@@ -1679,6 +1679,86 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ par
   }
 }
 
+// Product by G = M M^T without forming G (Remark 4's linear-time top-k
+// solvers: the work is linear in the kept entries), for the sampled
+// matricization M of the single tail mode (s head rows x MT tail columns),
+// on blocks of 32 float64 columns.  First W = M^T X, a wave per tail column
+// c: the column's entries (r, v) from the CSC list, lane j of each half
+// wave adding v X[r][j] over every second entry (the halves start one entry
+// apart), eight entries in flight; the two halves are added.  Loads are
+// unconditional at indices clamped into the column, and the extra entries'
+// values are zeroed (X is finite).
+__global__ __launch_bounds__(256) void k_spmm_cols(const Entry* __restrict__ coo_t,
+                                                   const uint32_t* __restrict__ colptr, uint32_t MT,
+                                                   FastDiv fMT, const double* __restrict__ X,
+                                                   uint32_t ldx, double* __restrict__ W, Status s) {
+  if (s.skip()) return;
+  const int lane = threadIdx.x & 63, j = lane & 31, half = lane >> 5;
+  const uint32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= MT) return;   // the whole wave (no barrier follows)
+  const uint32_t e0 = colptr[c], e1 = colptr[c + 1];
+  double acc = 0.0;
+  if (e1 > e0) {
+    for (uint32_t eb = e0 + half; eb < e1; eb += 16) {
+      Entry en[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) en[u] = coo_t[min(eb + 2u * u, e1 - 1)];
+      double q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = X[(size_t)fMT.div(en[u].l) * ldx + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        acc = fma((double)en[u].v * (eb + 2u * u < e1 ? 1.0 : 0.0), q[u], acc);
+    }
+  }
+  acc += __shfl_xor(acc, 32, 64);
+  if (half == 0) W[(size_t)c * 32 + j] = acc;
+}
+
+// Then C = al M W + be X + ga Xp (the filter epilogue of the products by G,
+// columns 0..31, ld ldc), a workgroup per head row r: its entries (c, v)
+// from the CSR list, eight groups of 32 lanes taking every eighth entry,
+// eight in flight per lane; the group sums are added in group order.
+__global__ __launch_bounds__(256) void k_spmm_rows(const Entry* __restrict__ coo_l,
+                                                   const uint32_t* __restrict__ rowptr, uint32_t MT,
+                                                   const double* __restrict__ W, double* __restrict__ C,
+                                                   uint32_t ldc, const double* __restrict__ X, Cheb ch,
+                                                   Status s) {
+  if (s.skip()) return;
+  __shared__ double part[8][32];
+  const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const uint32_t r = blockIdx.x;
+  const uint32_t e0 = rowptr[r], e1 = rowptr[r + 1];
+  const uint32_t base = r * MT;
+  double acc = 0.0;
+  if (e1 > e0) {
+    for (uint32_t eb = e0 + g; eb < e1; eb += 64) {
+      Entry en[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) en[u] = coo_l[min(eb + 8u * u, e1 - 1)];
+      double w[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) w[u] = W[(size_t)(en[u].l - base) * 32 + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        acc = fma((double)en[u].v * (eb + 8u * u < e1 ? 1.0 : 0.0), w[u], acc);
+    }
+  }
+  part[g][j] = acc;
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t += part[q][j];
+    const ChebCoef cf = cheb_coef(ch);
+    const size_t o = (size_t)r * ldc + j;
+    double v = cf.al * t;
+    if (cf.be != 0.0) v = fma(cf.be, X[o], v);
+    if (cf.ga != 0.0) v = fma(cf.ga, ch.Xp[o], v);
+    C[o] = v;
+  }
+}
+
 // Deterministic start block for the subspace iteration (hash of position).
 __global__ void k_ss_init(double* __restrict__ Q, uint32_t ldq, uint32_t M, uint32_t n,
                           const int32_t* tag, int32_t tagval, Status s) {
@@ -2066,6 +2146,33 @@ void gemm_sq(const Ctx& c, const double* G, uint32_t s, const double* X, double*
                        s, C, kBlock, X, ch, c.stat(with_done));
 }
 
+// The operator of the subspace iteration: a formed s x s Gram G, or (G
+// null) M M^T applied through the sparse layouts without forming it.
+struct SsOp {
+  const double* G;
+  const Entry* coo_l;
+  const uint32_t* rowptr;
+  const Entry* coo_t;
+  const uint32_t* colptr;
+  uint32_t MT;
+  FastDiv fMT;
+  double* W;   // MT x 32 float64
+};
+
+// C = op(X) through the filter epilogue (n columns; the sparse form takes
+// blocks of exactly 32).
+void apply_op(const Ctx& c, const SsOp& op, uint32_t s, const double* X, double* C, uint32_t n,
+              bool with_done, Cheb ch = Cheb{0, nullptr, 0, nullptr, nullptr}) {
+  if (op.G) {
+    gemm_sq(c, op.G, s, X, C, n, with_done, ch);
+    return;
+  }
+  hipLaunchKernelGGL(k_spmm_cols, dim3(cdiv(op.MT, 4)), dim3(256), 0, c.st, op.coo_t, op.colptr, op.MT,
+                     op.fMT, X, kBlock, op.W, c.stat(with_done));
+  hipLaunchKernelGGL(k_spmm_rows, dim3(s), dim3(256), 0, c.st, op.coo_l, op.rowptr, op.MT, op.W, C,
+                     kBlock, X, ch, c.stat(with_done));
+}
+
 void jacobi(const Ctx& c, const double* G, uint32_t nchunk, uint32_t n, double* V, double* lam,
             int32_t* tag, int32_t tagval, bool with_done, int rtop, double tol2 = kOffTol2) {
   JacArgs a;
@@ -2140,7 +2247,7 @@ double* orthonormalise(const Ctx& c, double* X, double* Y, uint32_t M, uint32_t 
 // remaining steps are skipped on the device).  Q (s x 64, ld 64) holds the
 // start block (warm start if *tag == tagval); on return its first R columns
 // are the Ritz vectors and lam the Ritz values, descending.
-void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double* Q, double* lam,
+void subspace_topk(const Ctx& c, const SsOp& op, uint32_t s, uint32_t R, double* Q, double* lam,
                    int32_t* tag, int32_t tagval, int maxit, int32_t* stat_it,
                    SolveTol tol = solve_tol(MACH_F32)) {
   uint32_t b = 2 * R;
@@ -2182,7 +2289,7 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
       ch.Xp = xpair;
       z = other(cur, xpair);
     }
-    gemm_sq(c, G, s, cur, z, b, true, ch);
+    apply_op(c, op, s, cur, z, b, true, ch);
     if (!rr) {
       if (it % 2 == 1) z = orthonormalise(c, z, other(z, nullptr), s, b, 1, true);
       cur = z;
@@ -2191,7 +2298,7 @@ void subspace_topk(const Ctx& c, const double* G, uint32_t s, uint32_t R, double
     double* w = other(z, nullptr);
     z = orthonormalise(c, z, w, s, b, 2, true);   // result back in z
     w = other(z, nullptr);
-    gemm_sq(c, G, s, z, w, b, true);               // w = G z
+    apply_op(c, op, s, z, w, b, true);             // w = G z
     uint32_t nchunk = cdiv(s, 32);
     if (nchunk > 64) nchunk = 64;
     uint32_t rows = cdiv(s, nchunk);
@@ -2473,7 +2580,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
   const double* G = c.d(SL.G);
   double* V = c.d(m.Q64);
   const uint32_t ldv = kBlock;
-  subspace_topk(c, G, m.s, m.R, V, c.d(m.lam), c.tags() + k, tagval, 24,
+  subspace_topk(c, SsOp{G}, m.s, m.R, V, c.d(m.lam), c.tags() + k, tagval, 24,
                 (int32_t*)(ws + SL.status + 96) + k, tol);
   if (m.kside) {
     uint32_t J = m.O * m.Q;
@@ -2493,11 +2600,20 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
 hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const SolverLayout& SL,
                              char* ws, int n, int R, double* A_out, hipStream_t st) {
   Ctx c{&SL, ws, sp.hdr, st};
-  hipError_t e = sparse_tail_gram_ok(si, SL, n) ? launch_gram_tail_sparse(si, sp, SL, ws, st)
-                                                : launch_gram_xhat(si, sp, SL, ws, n, st);
+  // the single tail mode beyond the sparse Gram's head rows: no Gram, the
+  // subspace iteration applies M M^T through the sparse layouts (blocks of
+  // 2R <= 32 columns)
+  const bool gram_free = SL.hosvd_gram_free && n == si.d - 1;
+  if (gram_free && 2 * R > 32) return hipErrorInvalidValue;
+  hipError_t e = gram_free ? hipSuccess
+                 : sparse_tail_gram_ok(si, SL, n) ? launch_gram_tail_sparse(si, sp, SL, ws, st)
+                                                  : launch_gram_xhat(si, sp, SL, ws, n, st);
   if (e != hipSuccess) return e;
   const uint32_t s = SL.hosvd_s[n];
   const double* G = c.d(SL.G);
+  const SsOp op = gram_free ? SsOp{nullptr, sp.coo_l, sp.rowptr, sp.coo_t, sp.colptr, si.MT, si.fMT,
+                                   c.d(SL.gfw)}
+                            : SsOp{G};
   double* V = c.d(SL.Qhs);
   double* lam = c.d(SL.lamH) ;
   uint32_t ldv;
@@ -2530,7 +2646,7 @@ hipError_t launch_hosvd_mode(const ShapeInfo& si, const SparsePtrs& sp, const So
     jacobi(c, G, 1, s, V, lam, tagc, 0x48000000 | (int32_t)s, false, R);
   } else {
     ldv = kBlock;
-    subspace_topk(c, G, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 48,
+    subspace_topk(c, op, s, (uint32_t)R, V, lam, tagc, 0x48000000 | (int32_t)s, 48,
                   (int32_t*)(ws + SL.status + 128) + n);
   }
   const uint32_t I = si.dims[n];

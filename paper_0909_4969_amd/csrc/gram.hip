@@ -207,7 +207,6 @@ hipError_t gram_run(GramArgs a, Load ld, double* G, size_t part_elems, hipStream
 // takes its terms in column order, each product v v' of two float32 values
 // is exact in float64, and every sum is rounded exactly as a plain
 // read-add-write would round it.
-constexpr uint32_t kSparseGramMaxRows = 2048;
 constexpr int kSgU = 4, kSgC = 4;
 
 __device__ __forceinline__ void sg_add(double* row, FastDiv fMT, Entry b, double vk) {

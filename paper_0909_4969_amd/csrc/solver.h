@@ -44,6 +44,10 @@ constexpr uint32_t kBlock = 64;          // subspace block for sides > kSmallEig
 // sred: Gram of a sweep mode (64 x 64), C_j of up to 3 other modes (3 x 256),
 // 16 x 16 Gram of a tall factor
 constexpr uint32_t kSredGram = 0, kSredCtc = 4096, kSredTall = 4096 + 768, kSredElems = 4096 + 768 + 256;
+// Column-side Gram of the single tail mode from the sparse layouts: at most
+// this many head rows (one float64 accumulator row per wave in LDS); beyond
+// it the mode's HOSVD runs without forming the Gram.
+constexpr uint32_t kSparseGramMaxRows = 2048;
 constexpr uint32_t kSplitK = 128;        // summation slice of the split products by G
 constexpr uint32_t kMfmaGramMaxRows = 1024;  // row-side HOSVD Grams on MFMA up to this side
 // Tiled head-row pass: the tail factor is tiled when its float32 copy (16
@@ -74,18 +78,22 @@ struct SolverLayout {
   size_t pv, pi;                         // column-max partials (1024 x 16)
   size_t tags;                           // int32 tags of warm starts and early exits (16)
   size_t sred;                           // float64 reduced partials (kSredElems)
+  size_t gfw;                            // Gram-free tail HOSVD: float64 MT x 32 block (else 0 bytes)
   // Tiled head-row pass (one tail mode whose factor is too large for LDS):
   // float32 partial rows, tiles x MH x 16; 0 when the pass is not tiled.
   size_t tpart;
   // A second copy of the scratch above (G .. sred), used by the HOSVD of the
   // last mode when it runs on its own stream beside the other modes; 0 when
   // there is none (d == 1).
-  size_t laneb[17];
+  size_t laneb[18];
   size_t total;
   int ident_last;                        // the last mode is left uncompressed (Tucker-n)
   ModePlan mp[kMaxD];
   uint32_t KT, KH, hosvd_s[kMaxD];
   int hosvd_kside[kMaxD];
+  // The last mode's HOSVD runs without forming its Gram (the single tail
+  // mode, column side, more head rows than the sparse Gram holds).
+  int hosvd_gram_free;
 };
 
 bool make_solver_layout(const ShapeInfo& si, const int32_t* ranks, SolverLayout* out);
