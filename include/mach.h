@@ -160,7 +160,10 @@ size_t mach_solver_workspace_bytes(const mach_shape* s, const int32_t* ranks,
 /* MACH-HOSVD factors (Alg. 1, the HOSVD loop): for every mode n,
  * A^(n) = R_n leading left singular vectors of Xhat_(n), from the Gram
  * matrix of the sampled matricization on its smaller side and a float64
- * eigensolve.  ws_sample must hold a completed mach_sample of the same
+ * eigensolve.  The Gram of the layouts' single tail mode on its column side
+ * with more than 2048 head rows is not formed: its eigensolve applies it as
+ * two sparse products (Remark 4; the workspace then holds no such Gram).
+ * ws_sample must hold a completed mach_sample of the same
  * shape.  A_dev is a host array of d device pointers, each I_n x R_n
  * float64 row-major, written.  nnz_cap is the capacity ws_sample was built
  * with (it fixes where the sparse arrays sit).  Requires
