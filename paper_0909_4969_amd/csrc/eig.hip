@@ -1784,21 +1784,47 @@ __global__ void k_copy64(const double* __restrict__ src, double* __restrict__ ds
 
 // Residuals of the top R Ritz pairs: converged if all
 // ||Z2[:,r] - theta_r Qr[:,r]|| <= tol * theta_0; single workgroup.
-__global__ __launch_bounds__(256) void k_ss_check(const double* __restrict__ Z2, const double* __restrict__ Qr,
+constexpr int kSsCheckThreads = 512;
+
+__global__ __launch_bounds__(kSsCheckThreads) void k_ss_check(const double* __restrict__ Z2, const double* __restrict__ Qr,
                                                   uint32_t ld, uint32_t M, const double* __restrict__ theta,
                                                   uint32_t R, double tol, double tol_fail, int32_t* done, int last,
                                                   int32_t* stat_it, int32_t it, int32_t* ritz,
                                                   Status s) {
   if (s.skip()) return;
-  __shared__ double res[16][4];
+  constexpr int NW = kSsCheckThreads / 64;
+  __shared__ double res[16][NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double acc[16];
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-  for (uint32_t m = threadIdx.x; m < M; m += 256)
-    for (uint32_t r = 0; r < R; ++r) {
-      double d = Z2[(size_t)m * ld + r] - theta[r] * Qr[(size_t)m * ld + r];
-      acc[r] += d * d;
+  double th[16], acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    th[r] = theta[min((uint32_t)r, R - 1)];
+    acc[r] = 0.0;
+  }
+  // two rows per thread and round, the 16 columns of both blocks loaded
+  // unconditionally (columns from R on repeat column R - 1, rows past M
+  // repeat row M - 1; their terms are zeroed)
+  for (uint32_t m0 = threadIdx.x; m0 < M; m0 += 2 * kSsCheckThreads) {
+    double z[2][16], q[2][16];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const size_t row = (size_t)min(m0 + h * kSsCheckThreads, M - 1) * ld;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        z[h][r] = Z2[row + min((uint32_t)r, R - 1)];
+        q[h][r] = Qr[row + min((uint32_t)r, R - 1)];
+      }
     }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double keep = m0 + h * kSsCheckThreads < M ? 1.0 : 0.0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const double d = (z[h][r] - th[r] * q[h][r]) * keep;
+        acc[r] = fma(d, d, acc[r]);
+      }
+    }
+  }
   for (int r = 0; r < 16; ++r) {
     double v = acc[r];
 #pragma unroll
@@ -1809,7 +1835,9 @@ __global__ __launch_bounds__(256) void k_ss_check(const double* __restrict__ Z2,
   if (threadIdx.x == 0) {
     double worst = 0.0;
     for (uint32_t r = 0; r < R; ++r) {
-      double v = sqrt((res[r][0] + res[r][1]) + (res[r][2] + res[r][3]));
+      double t = 0.0;
+      for (int q = 0; q < NW; ++q) t += res[r][q];
+      const double v = sqrt(t);
       worst = v > worst ? v : worst;
     }
     double ref = fabs(theta[0]);
@@ -2189,7 +2217,7 @@ void jacobi(const Ctx& c, const double* G, uint32_t nchunk, uint32_t n, double* 
   if (n <= 16)
     hipLaunchKernelGGL((k_jacobi_small<16, 256>), dim3(1), dim3(256), 0, c.st, a);
   else if (n <= 32)
-    hipLaunchKernelGGL((k_jacobi_small<32, 256>), dim3(1), dim3(256), 0, c.st, a);
+    hipLaunchKernelGGL((k_jacobi_small<32, 512>), dim3(1), dim3(512), 0, c.st, a);
   else
     hipLaunchKernelGGL((k_jacobi_small<64, 1024>), dim3(1), dim3(1024), 0, c.st, a);
 }
@@ -2313,7 +2341,7 @@ void subspace_topk(const Ctx& c, const SsOp& op, uint32_t s, uint32_t R, double*
     double* zr = other(z, w);
     gemm(c, z, kBlock, VH, b, Qr, kBlock, s, b, b, true);
     gemm(c, w, kBlock, VH, b, zr, kBlock, s, b, b, true);
-    hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(256), 0, c.st, zr, Qr, kBlock, s, lamH, R, tol.res, tol.res_fail,
+    hipLaunchKernelGGL(k_ss_check, dim3(1), dim3(kSsCheckThreads), 0, c.st, zr, Qr, kBlock, s, lamH, R, tol.res, tol.res_fail,
                        tags + kTagDone, last ? 1 : 0, stat_it, it, tags + kTagRitz, c.stat(true));
     cur = Qr;
   }
