@@ -1326,15 +1326,28 @@ __global__ __launch_bounds__(256) void k_gemm64(const double* __restrict__ A, ui
   const uint32_t m0 = blockIdx.x * 16;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (uint32_t k0 = 0; k0 < K; k0 += 64) {
-    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      int r = e >> 6, c = e & 63;
-      uint32_t m = m0 + r, k = k0 + c;
-      As[r][c] = (m < M && k < K) ? A[(size_t)m * lda + k] : 0.0;
+    // all tile loads issued before any is stored: unconditional, at indices
+    // clamped into A and B (finite), the outside entries zeroed by a factor 0
+    double va[4], vb[16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = threadIdx.x + 256 * t, r = e >> 6, c = e & 63;
+      va[t] = A[(size_t)min(m0 + r, M - 1) * lda + min(k0 + c, K - 1)];
     }
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-      int r = e >> 6, c = e & 63;
-      uint32_t k = k0 + r;
-      Bs[r][c] = (k < K && (uint32_t)c < N) ? B[(size_t)k * ldb + c] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = threadIdx.x + 256 * t, r = e >> 6, c = e & 63;
+      vb[t] = B[(size_t)min(k0 + r, K - 1) * ldb + min((uint32_t)c, N - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = threadIdx.x + 256 * t, r = e >> 6, c = e & 63;
+      As[r][c] = va[t] * ((m0 + r < M && k0 + c < K) ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = threadIdx.x + 256 * t, r = e >> 6, c = e & 63;
+      Bs[r][c] = vb[t] * ((k0 + r < K && (uint32_t)c < N) ? 1.0 : 0.0);
     }
     __syncthreads();
 #pragma unroll 8
@@ -1366,12 +1379,22 @@ __global__ __launch_bounds__(256) void k_atb_partial(const double* __restrict__ 
   const uint32_t r0 = blockIdx.x * rows, r1 = min(M, r0 + rows);
   double acc[4][4] = {};
   for (uint32_t m0 = r0; m0 < r1; m0 += 32) {
-    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-      int r = e >> 6, c = e & 63;
-      uint32_t m = m0 + r;
-      bool ok = m < r1 && (uint32_t)c < n;
-      As[r][c] = ok ? A[(size_t)m * lda + c] : 0.0;
-      Bs[r][c] = ok ? B[(size_t)m * ldb + c] : 0.0;
+    // loads unconditional at clamped indices (finite), then stored with the
+    // outside entries zeroed by a factor 0
+    double va[8], vb[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = threadIdx.x + 256 * t, r = e >> 6, c = e & 63;
+      const size_t mm = min(m0 + r, r1 - 1), cc = min((uint32_t)c, n - 1);
+      va[t] = A[mm * lda + cc];
+      vb[t] = B[mm * ldb + cc];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = threadIdx.x + 256 * t, r = e >> 6, c = e & 63;
+      const double ok = (m0 + r < r1 && (uint32_t)c < n) ? 1.0 : 0.0;
+      As[r][c] = va[t] * ok;
+      Bs[r][c] = vb[t] * ok;
     }
     __syncthreads();
     for (int rr = 0; rr < 32; ++rr) {
