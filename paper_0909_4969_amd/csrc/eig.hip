@@ -514,12 +514,6 @@ struct SnapArgs {
   int n;
 };
 
-__global__ void k_snapshot(SnapArgs a, Status s) {
-  if (s.skip()) return;
-  const int j = blockIdx.y;
-  const uint32_t e = blockIdx.x * 256 + threadIdx.x;
-  if (j < a.n && e < a.n4[j]) a.dst[j][e] = a.src[j][e];
-}
 
 struct CtcArgs {
   const float* old[3];
@@ -576,11 +570,7 @@ struct ReduceArgs {
   uint32_t nch[4];
 };
 
-__global__ __launch_bounds__(256) void k_reduce_chunks(ReduceArgs a, Status s) {
-  if (s.skip()) return;
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (e >= a.nent) return;
+__device__ __forceinline__ void reduce_entry(const ReduceArgs& a, uint32_t e, uint32_t lane) {
   const uint32_t nc = a.nch[e / a.gsize];
   const double* p = a.in + (size_t)e * a.es;
   double v = 0.0;
@@ -588,6 +578,21 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(ReduceArgs a, Status s) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   if (lane == 0) a.out[e] = v;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_chunks(ReduceArgs a, Status s) {
+  if (s.skip()) return;
+  const uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e < a.nent) reduce_entry(a, e, threadIdx.x & 63);
+}
+
+// Two independent sets of sums in one launch: the entries of b follow
+// those of a.
+__global__ __launch_bounds__(256) void k_reduce_chunks2(ReduceArgs a, ReduceArgs b, Status s) {
+  if (s.skip()) return;
+  const uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e < a.nent) reduce_entry(a, e, threadIdx.x & 63);
+  else if (e - a.nent < b.nent) reduce_entry(b, e - a.nent, threadIdx.x & 63);
 }
 
 // Column-side mode with a short side (I <= 128, K <= 64, R <= 8): instead
@@ -1172,15 +1177,35 @@ __global__ __launch_bounds__(NT) void k_mode_solve(SolveArgs a) {
 
 // Column-side back-projection Aw = Y_(k) M (I x 16, float64) from the
 // float32 view (O, I, Q) of Y_k, plus per-workgroup partials of Aw^T Aw.
+// Workgroups from nwg on copy the other modes' float32 factors for the next
+// sweep's warm start instead (snapshot; they take no part in the rest).
 __global__ __launch_bounds__(256) void k_bp_tall(const float* __restrict__ Y, uint32_t O, uint32_t I,
                                                  uint32_t Q, const double* __restrict__ M, uint32_t R,
                                                  double* __restrict__ Aw, double* __restrict__ part,
+                                                 uint32_t nwg, SnapArgs sa, uint32_t snap_wg,
                                                  Status s) {
   if (s.skip()) return;
+  if (blockIdx.x >= nwg) {   // whole workgroups, before any barrier
+    const uint32_t b = blockIdx.x - nwg, j = b / snap_wg;
+    const uint32_t e = (b % snap_wg) * 256 + threadIdx.x;
+    if ((int)j < sa.n && e < sa.n4[j]) sa.dst[j][e] = sa.src[j][e];
+    return;
+  }
   __shared__ double Ms[256][17];
   __shared__ double rows[256][17];
   const uint32_t K = O * Q;
-  for (uint32_t e = threadIdx.x; e < K * 16; e += 256) Ms[e >> 4][e & 15] = M[e];
+  {
+    // M (K x 16, K <= 256) staged with unconditional loads at clamped
+    // indices; the rows from K on (unused) get zeros
+    double mv[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) mv[t] = M[min(threadIdx.x + 256u * t, K * 16 - 1)];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const uint32_t e = threadIdx.x + 256u * t;
+      Ms[e >> 4][e & 15] = mv[t] * (e < K * 16 ? 1.0 : 0.0);
+    }
+  }
   __syncthreads();
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   double acc[16];
@@ -1189,11 +1214,19 @@ __global__ __launch_bounds__(256) void k_bp_tall(const float* __restrict__ Y, ui
   if (i < I) {
     for (uint32_t o = 0; o < O; ++o) {
       const float* yrow = Y + ((size_t)o * I + i) * Q;
-      for (uint32_t q = 0; q < Q; ++q) {
-        double y = (double)yrow[q];
-        const uint32_t kappa = o * Q + q;
+      // eight entries of the row per round, loaded before any is used
+      // (clamped to the row; the extra ones weigh 0)
+      for (uint32_t q0 = 0; q0 < Q; q0 += 8) {
+        float yv[8];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = fma(y, Ms[kappa][r], acc[r]);
+        for (int u = 0; u < 8; ++u) yv[u] = yrow[min(q0 + u, Q - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double y = (double)yv[u] * (q0 + u < Q ? 1.0 : 0.0);
+          const uint32_t kappa = o * Q + min(q0 + u, Q - 1);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[r] = fma(y, Ms[kappa][r], acc[r]);
+        }
       }
     }
 #pragma unroll
@@ -2488,6 +2521,7 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
     a.ctc = nullptr;
     a.cstride = kCtcChunks;
     a.nother = 0;
+    ReduceArgs rctc{};
     if (m.kside) {
       CtcArgs ca{};
       for (int j = 0; j < si.d; ++j) {
@@ -2504,7 +2538,8 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
       a.nother = ca.n;
       hipLaunchKernelGGL(k_ctc_partial, dim3(kCtcChunks, ca.n), dim3(256), 0, st, ca, c.d(SL.part),
                          c.stat());
-      // C_j of every other mode summed once (one wave per entry)
+      // C_j of every other mode summed once (one wave per entry), in the
+      // same launch as the Gram partials' sums below when there are any
       ReduceArgs r{};
       r.in = c.d(SL.part);
       r.out = c.d(SL.sred) + kSredCtc;
@@ -2516,23 +2551,28 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
         r.nch[j] = ca.nch[j];
         a.onch[j] = 1;
       }
-      hipLaunchKernelGGL(k_reduce_chunks, dim3(cdiv(r.nent, 4)), dim3(256), 0, st, r, c.stat());
+      rctc = r;
       a.ctc = r.out;
       a.cstride = 1;
     }
+    ReduceArgs rg{};
     if (nchunk > 1) {   // the Gram partials likewise
-      ReduceArgs r{};
-      r.in = c.d(SL.Gpart);
-      r.out = c.d(SL.sred) + kSredGram;
-      r.nent = m.s * m.s;
-      r.gsize = r.nent;
-      r.es = nchunk;
-      r.cs = 1;
-      r.nch[0] = nchunk;
-      hipLaunchKernelGGL(k_reduce_chunks, dim3(cdiv(r.nent, 4)), dim3(256), 0, st, r, c.stat());
-      a.part = r.out;
+      rg.in = c.d(SL.Gpart);
+      rg.out = c.d(SL.sred) + kSredGram;
+      rg.nent = m.s * m.s;
+      rg.gsize = rg.nent;
+      rg.es = nchunk;
+      rg.cs = 1;
+      rg.nch[0] = nchunk;
+      a.part = rg.out;
       nchunk = 1;
     }
+    if (rctc.nent && rg.nent)
+      hipLaunchKernelGGL(k_reduce_chunks2, dim3(cdiv(rctc.nent + rg.nent, 4)), dim3(256), 0, st, rctc, rg,
+                         c.stat());
+    else if (rctc.nent || rg.nent)
+      hipLaunchKernelGGL(k_reduce_chunks, dim3(cdiv(rctc.nent + rg.nent, 4)), dim3(256), 0, st,
+                         rctc.nent ? rctc : rg, c.stat());
     a.nchunk = nchunk;
     a.s = m.s;
     a.I = m.I;
@@ -2590,11 +2630,13 @@ hipError_t launch_mode_update(const ShapeInfo& si, const SolverLayout& SL, char*
         nmax = std::max(nmax, sa.n4[sa.n]);
         ++sa.n;
       }
-      hipLaunchKernelGGL(k_snapshot, dim3(cdiv(nmax, 256), sa.n), dim3(256), 0, st, sa, c.stat());
       uint32_t nwg = cdiv(m.I, 256);
       double* part = c.d(SL.part);
-      hipLaunchKernelGGL(k_bp_tall, dim3(nwg), dim3(256), 0, st, (const float*)(ws + m.ybuf), m.O, m.I,
-                         m.Q, c.d(SL.small), m.R, c.d(SL.Aw), part, c.stat());
+      // the back-projection, with the snapshot in extra workgroups
+      const uint32_t snap_wg = cdiv(nmax, 256);
+      hipLaunchKernelGGL(k_bp_tall, dim3(nwg + snap_wg * (uint32_t)sa.n), dim3(256), 0, st,
+                         (const float*)(ws + m.ybuf), m.O, m.I, m.Q, c.d(SL.small), m.R, c.d(SL.Aw),
+                         part, nwg, sa, snap_wg, c.stat());
       const double* g16 = reduce_tall(c, part, nwg);
       hipLaunchKernelGGL(k_chol_apply_tall, dim3(nwg), dim3(256), 0, st, c.d(SL.Aw), m.I, m.R, g16, 1u,
                          c.d(SL.pv), (uint32_t*)(ws + SL.pi), c.stat());
