@@ -1635,17 +1635,34 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ par
   __shared__ double trs;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nn = (int)n, nb = (nn + 15) / 16, E = nb * 16;
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    double v = (r == c) ? 1.0 : 0.0;
-    if (r < nn && c < nn) {
-      const double* p = part + (size_t)(r * n + c) * nchunk;
-      v = 0.0;
-#pragma unroll 16
-      for (uint32_t ch = 0; ch < nchunk; ++ch) v += p[ch];
+  {
+    // S summed from its partials in chunk order, the 16 entries of a thread
+    // loaded together (unconditionally, at indices clamped into the n x n
+    // partials, the outside ones zeroed by a factor 0), then the padding
+    // set to the identity
+    constexpr int NE = 64 * 64 / 256;
+    double g[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) g[u] = 0.0;
+    for (uint32_t ch = 0; ch < nchunk; ++ch) {
+      double pv[NE];
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = tid + 256 * u, r = e >> 6, c = e & 63;
+        pv[u] = part[(size_t)(min(r, nn - 1) * nn + min(c, nn - 1)) * nchunk + ch];
+      }
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = tid + 256 * u, r = e >> 6, c = e & 63;
+        g[u] += pv[u] * ((r < nn && c < nn) ? 1.0 : 0.0);
+      }
     }
-    A[r][c] = v;
-    Li[r][c] = 0.0;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + 256 * u, r = e >> 6, c = e & 63;
+      A[r][c] = (r < nn && c < nn) ? g[u] : (r == c ? 1.0 : 0.0);
+      Li[r][c] = 0.0;
+    }
   }
   __syncthreads();
   if (tid < 64) {

@@ -579,6 +579,23 @@ __global__ __launch_bounds__(256) void k_dense_ttm(const float* __restrict__ in,
     uint32_t o = (uint32_t)(t / R);
     const float* src = in + (size_t)o * I * Q + q;
     uint32_t i = w;
+    // four steps of the loop below at a time, their loads issued first (the
+    // same additions in the same order)
+    for (; i + 28 < I; i += 32) {
+      float a[8], x[8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[2 * u] = A[(size_t)(i + 8 * u) * 16 + r];
+        x[2 * u] = src[(size_t)(i + 8 * u) * Q];
+        a[2 * u + 1] = A[(size_t)(i + 8 * u + 4) * 16 + r];
+        x[2 * u + 1] = src[(size_t)(i + 8 * u + 4) * Q];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc0 = fmaf(a[2 * u], x[2 * u], acc0);
+        acc1 = fmaf(a[2 * u + 1], x[2 * u + 1], acc1);
+      }
+    }
     for (; i + 4 < I; i += 8) {
       acc0 = fmaf(A[(size_t)i * 16 + r], src[(size_t)i * Q], acc0);
       acc1 = fmaf(A[(size_t)(i + 4) * 16 + r], src[(size_t)(i + 4) * Q], acc1);
