@@ -44,6 +44,18 @@ def test_status_strings(M):
     assert M.status_string(-99)
 
 
+def test_gram_free_tail_hosvd_reserves_no_gram(M):
+    # 48 x 48 = 2304 head rows, more than the sparse tail Gram holds: the
+    # tail mode's HOSVD Gram (2304^2 float64) is never formed, so this window
+    # needs less solver workspace than a smaller one with 2016 head rows,
+    # whose 2016^2 Gram (32.5 MB) is reserved in each of its two lanes
+    ranks = (8, 8, 16)
+    formed = M.solver_workspace_bytes((48, 42, 4096), ranks, 1000)
+    gram_free = M.solver_workspace_bytes((48, 48, 4096), ranks, 1000)
+    assert formed > 0 and gram_free > 0
+    assert gram_free < formed
+
+
 def test_size_queries(M):
     shape, ranks = (128, 16, 16384), (8, 4, 16)
     cap = M.nnz_capacity(shape, 0.1)
