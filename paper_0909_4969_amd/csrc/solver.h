@@ -82,7 +82,7 @@ struct SolverLayout {
   // Tiled head-row pass (one tail mode whose factor is too large for LDS):
   // float32 partial rows, tiles x MH x 16; 0 when the pass is not tiled.
   size_t tpart;
-  // A second copy of the scratch above (G .. sred), used by the HOSVD of the
+  // A second copy of the scratch above (G .. gfw), used by the HOSVD of the
   // last mode when it runs on its own stream beside the other modes; 0 when
   // there is none (d == 1).
   size_t laneb[18];
