@@ -54,7 +54,7 @@ constexpr uint32_t kMfmaGramMaxRows = 1024;  // row-side HOSVD Grams on MFMA up 
 // columns) exceeds kTiledFactorBytes; tiles span kTileTicksMin..kTileTicksMax
 // ticks.
 constexpr uint32_t kTiledFactorBytes = 16384;
-constexpr uint32_t kTileTicksMin = 128, kTileTicksMax = 512;
+constexpr uint32_t kTileTicksMin = 128, kTileTicksMax = 256;
 
 // Status region: int32 status word at +0, int32 tags[16] at +16 (eigen
 // warm-start tags of modes 0..7, then kTagRR, kTagCold, kTagDone), int32

@@ -427,8 +427,9 @@ inline uint32_t tiled_rows_per_block(double density, int lpe) {
 
 template <int RI, int BF>
 hipError_t go_tiled(TiledArgs a, hipStream_t st) {
-  // Ticks per tile: the largest of 512, 256, 128 that still gives at least
-  // 1024 workgroups (or the smallest).
+  // Ticks per tile: the largest of 256 and 128 that still gives at least
+  // 1024 workgroups (or the smallest).  Tiles of 256 (2048 workgroups on the
+  // monitoring window) beat 512 and 1024 in spite of twice the partial rows.
   const uint32_t nrb = (a.MH + a.RB - 1) / a.RB;
   uint32_t tc = kTileTicksMax;
   while (tc > kTileTicksMin && (size_t)nrb * ((a.MT + tc - 1) / tc) < 1024) tc /= 2;
