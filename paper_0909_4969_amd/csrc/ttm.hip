@@ -357,8 +357,15 @@ __global__ __launch_bounds__(256) void k_rows_tiled(TiledArgs a) {
         const uint32_t e = e0 + LPE * j + quad;
         en[j] = e < hi ? ent64[e] : dummy;
       }
+      // Step j holds entries e0 + LPE j .. e0 + LPE j + LPE - 1, of which
+      // some exist only while LPE j < hi - e0.  The test is the same in the
+      // LPE lanes of a row (a broadcast never reads a masked lane), and a
+      // wave skips the step once every row in it is done, instead of
+      // reading factor rows from LDS for weight-0 slots.
+      const uint32_t left = hi - e0;
 #pragma unroll
       for (int j = 0; j < kLoad; ++j) {
+        if ((uint32_t)(LPE * j) >= left) continue;
 #pragma unroll
         for (int q = 0; q < LPE; ++q) {
           const uint32_t l = group_bcast<LPE>((uint32_t)en[j], q);
