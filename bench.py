@@ -246,7 +246,7 @@ def trace_summary(d):
     rd = os.path.relpath(d, ROOT)
     lines = ["# Kernel time of the benchmark run (monitoring window 128 x 16 x 16384 and voxel "
              "workload 64 x 64 x 64 x 256)", "",
-             "Command (GPU box, repository root as `$R`):", "",
+             "Command (on the MI355X machine, repository root as `$R`):", "",
              "    cd /tmp && export TMPDIR=/tmp && timeout -k 10 300 rocprofv3 --kernel-trace --stats \\",
              f"      --output-format csv -d $R/{rd} -o run -- \\",
              "      python3 $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline --serve-requests 0",
