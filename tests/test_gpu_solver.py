@@ -56,6 +56,9 @@ def _gramfree():
 def _gramfree_sparse():
     X, _ = synth.workload2(shape=(48, 48, 4096), seed=23)
     return X, (8, 8, 16), 0.0015, 31
+def _dense_p07():
+    X, _ = synth.workload2(shape=(32, 16, 2048), seed=25)
+    return X, (8, 4, 16), 0.7, 26
 
 # monitor-128x16x2048: mode 0 has I = 128 > K = 64 with R = 8, the column-side
 # block subspace iteration on Y Y^T.  Sweep Grams with a side above 64 (the
@@ -68,14 +71,17 @@ def _gramfree_sparse():
 # the sparse tail Gram holds (48 x 48 = 2304 > 2048): the tail mode's HOSVD
 # never forms its Gram (products by M M^T through the sparse layouts); at
 # p = 0.0015 about 3.4 entries fall in each tail column and 136 of the 4096
-# columns keep none, so those products meet empty columns and rows.
+# columns keep none, so those products meet empty columns and rows.  At p =
+# 0.7 (monitor-p0.7) the tail mode's 512-row sparse Gram has columns of about
+# 360 kept entries, so column parts run past the four 64-entry chunks its
+# walk loads at once (the loop for longer parts).
 CASES = {"tucker-64x32x48-f64": _w1, "monitor-32x16x2048": _w2, "monitor-128x16x2048": _w2s,
          "monitor-p0.01-64x16x4096": _w2p01,
          "voxel-16x16x16x64": _w3, "matrix-300x200": _mat, "sides>64-96x80x6": _big_side,
          "rowside96-96x12x12": _row96, "colside216-16x16x16x256": _col216,
          "colside100-600x12x12": _col100, "rowside48-48x12x12": _row48,
          "rowside64r12-64x12x12": _row64r12, "gramfree-48x48x4096": _gramfree,
-         "gramfree-p0.0015-48x48x4096": _gramfree_sparse}
+         "gramfree-p0.0015-48x48x4096": _gramfree_sparse, "monitor-p0.7-32x16x2048": _dense_p07}
 
 # Core and error bars.  The float32 bar is 1e-5 relative (norm-wise) on the
 # core, so 2e-5 relative on its squared norm (d||G||^2 / ||G||^2 = 2 d||G|| /
